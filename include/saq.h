@@ -1,0 +1,177 @@
+/*
+ * saq.h -- C ABI of the MI355X SAQ encoder (libsaq.so).
+ *
+ * SAQ: "Pushing the Limits of Vector Quantization through Code Adjustment and
+ * Dimension Segmentation" (SIGMOD'26, arXiv 2509.12086).
+ *
+ * Conventions shared by every entry point
+ *   - Status codes: every call returns saq_status; on failure
+ *     saq_last_error() (thread-local) holds a message.  Nothing throws.
+ *   - Device buffers (inputs, codes, factors, workspaces, the uploaded plan)
+ *     are caller-owned device memory on the current HIP device.  The library
+ *     allocates no device memory.  Plan handles are library-owned host
+ *     objects, freed with saq_plan_free.
+ *   - Asynchrony: device calls enqueue work on `stream` (a hipStream_t passed
+ *     as void*, NULL = the default stream) and return; results are valid
+ *     after the stream is synchronised, and inputs must stay alive until then.
+ *   - n == 0 is a no-op.  Negative sizes, NULL required pointers, a workspace
+ *     smaller than the matching *_workspace_bytes() or a plan that was not
+ *     uploaded give SAQ_EINVAL; a failed launch gives SAQ_EDEVICE.
+ *   - Inputs must be finite.  Non-finite inputs give unspecified codes but
+ *     never an out-of-bounds access.
+ *
+ * Record layout (per encoded vector)
+ *   codes   : code_bytes bytes.  For each kept segment (bits B > 0) in plan
+ *             order, B bit-planes, most significant first; plane p holds bit
+ *             p of the segment's W codes, dimension i at byte i/8, bit i%8;
+ *             a plane takes ceil(W/8) bytes.  (The paper stores a B*D-bit
+ *             string, end of Section 3.1; the plane order keeps every b-bit
+ *             prefix a valid b-bit code, Section 3.2.)
+ *   factors : n_kept + 1 floats: f_s = ||o_s||^2 / <u_s, o_s> for each kept
+ *             segment (u = code - (2^B - 1)/2), then ||o||^2 = ||x - c||^2.
+ *             The paper stores the norm and <o_a, o> (end of Section 3.1);
+ *             f_s carries the same information for the estimator of
+ *             Section 3.2: <o_s, q_s> ~= f_s <u_s, q_s>.
+ */
+#ifndef SAQ_H
+#define SAQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAQ_OK = 0,
+    SAQ_EINVAL = 1,        /* bad argument */
+    SAQ_ENOMEM = 2,        /* host allocation failed */
+    SAQ_EDEVICE = 3,       /* HIP error (launch, copy) */
+    SAQ_EUNSUPPORTED = 4,  /* valid but not supported by this build */
+    SAQ_EIO = 5            /* plan file missing, truncated or corrupt */
+} saq_status;
+
+typedef struct saq_plan saq_plan;   /* opaque, library-owned */
+
+/* Plan-search parameters (Sections 4.1-4.2). */
+typedef struct {
+    double   bits_per_dim;    /* average budget B; Q_quota = floor(B * D) bits */
+    int32_t  granularity;     /* segment widths are multiples of g dims (paper: 64) */
+    int32_t  max_bits;        /* allowed bits per dim: 0..max_bits (<= 16) */
+    int32_t  max_width;       /* cap on the width of a segment with bits > 0, multiple of g (0 = none) */
+    double   seg_eps;         /* fewest segments whose modelled error is <= (1 + seg_eps) * minimum (paper: 0.1 %) */
+    int32_t  rotate_segments; /* 1: random orthonormal rotation inside each kept segment (Section 4.1) */
+    int64_t  fit_sample;      /* rows used for mean/covariance (0 = all); an evenly spaced subset */
+    uint64_t seed;            /* seeds the per-segment rotations */
+} saq_plan_params;
+
+typedef struct {
+    int32_t D;            /* input dimension */
+    int32_t D_kept;       /* dims in segments with bits > 0 (rows of M) */
+    int32_t n_seg;        /* all segments, including 0-bit ones */
+    int32_t n_kept;       /* segments with bits > 0 */
+    int64_t code_bytes;   /* bytes of one code record */
+    int32_t n_factors;    /* floats of one factor record = n_kept + 1 */
+    int32_t max_kept_width;
+    int32_t max_kept_bits;
+    double  model_error;  /* sum over segments of 2^-B * sum sigma_i^2 (Eq. seg-err without 1/pi) */
+    double  min_error;    /* minimum of the model over all plans within the quota */
+    int64_t quota_bits;   /* Q_quota */
+    int64_t used_bits;    /* sum B * |Seg| */
+} saq_plan_info;
+
+/* Defaults: B=4, g=16, max_bits=9, max_width=512, seg_eps=1e-3, rotation on,
+   fit_sample=65536, seed=1. */
+void saq_default_params(saq_plan_params* p);
+
+/* Fit a plan on host rows X [n x D] (row-major FP32): mean c, covariance and
+   its FP64 eigen-decomposition (Section 4.1, variances sorted descending),
+   the plan search of Algorithm 2 with the fewest-segments rule (Section 4.2),
+   per-segment random rotations, and M = blockdiag(R_s) P_kept rounded to FP32
+   (Eq. rotate; PCA and rotation folded into one matrix as Section 5.2 notes).
+   *out receives a new handle. */
+saq_status saq_fit_plan(const float* X, int64_t n, int32_t D,
+                        const saq_plan_params* p, saq_plan** out);
+
+/* Same as saq_fit_plan from a given basis: mean [D], eigenvectors [D x D]
+   row-major with eigenvector j in column j, eigenvalues [D] (any order; they
+   are sorted descending together with their vectors). */
+saq_status saq_plan_from_basis(const double* mean, const double* eigvecs,
+                               const double* eigvals, int32_t D,
+                               const saq_plan_params* p, saq_plan** out);
+
+/* A plan given explicitly: n_seg segments (widths summing to D, bits in
+   0..16), M [D_kept x D] FP32 row-major whose rows follow the kept segments
+   in order, c [D] FP32, and optional per-dim variances [D] (may be NULL). */
+saq_status saq_plan_from_parts(int32_t D, int32_t n_seg, const int32_t* widths,
+                               const int32_t* bits, const float* M, const float* c,
+                               const double* variances, saq_plan** out);
+
+saq_status saq_plan_info_get(const saq_plan* plan, saq_plan_info* out);
+/* widths/bits: arrays of n_seg entries (all segments, plan order). */
+saq_status saq_plan_segments(const saq_plan* plan, int32_t* widths, int32_t* bits);
+/* M [D_kept x D], c [D], variances [D]; any output may be NULL. */
+saq_status saq_plan_arrays(const saq_plan* plan, float* M, float* c, double* variances);
+/* Versioned binary file with a checksum; load gives SAQ_EIO on a bad file. */
+saq_status saq_plan_save(const saq_plan* plan, const char* path);
+saq_status saq_plan_load(const char* path, saq_plan** out);
+void saq_plan_free(saq_plan* plan);
+
+/* Device-resident copy of the plan: saq_plan_device_bytes() bytes of
+   caller-owned device memory, filled by saq_plan_upload (enqueued on stream;
+   the host staging copy is kept by the plan until it is freed).  A plan can
+   be uploaded again to another buffer; the last upload is the one used. */
+int64_t    saq_plan_device_bytes(const saq_plan* plan);
+saq_status saq_plan_upload(saq_plan* plan, void* dev_buf, void* stream);
+
+/* Encode n rows X_dev [n x D] (row-major FP32, device): o = M (x - c) with an
+   FP32 matrix-core GEMM (Eq. rotate), then for every kept segment the grid
+   quantization of Eq. (find_nearest_code) and `rounds` rounds of the code
+   adjustment of Algorithm 1 (stopping early once a round changes nothing,
+   which cannot alter the result), then the stored factors and the bit-plane
+   record.  codes_dev [n x code_bytes], factors_dev [n x n_factors].
+   ws_dev: saq_encode_workspace_bytes(plan, n) bytes of device scratch. */
+int64_t    saq_encode_workspace_bytes(const saq_plan* plan, int64_t n);
+saq_status saq_encode(const saq_plan* plan, const float* X_dev, int64_t n, int32_t rounds,
+                      uint8_t* codes_dev, float* factors_dev, void* ws_dev, int64_t ws_bytes,
+                      void* stream);
+
+/* Layouts of a projected-row buffer O with leading dimension ld:
+   SAQ_LAYOUT_ROWS: element (vector i, kept dim j) at O[i * ld + j], ld >= D_kept
+   SAQ_LAYOUT_DIMS: element (vector i, kept dim j) at O[j * ld + i], ld >= n,
+                    ld % 4 == 0 and O 16-byte aligned (what saq_encode uses
+                    internally: one coalesced row per kept dim) */
+#define SAQ_LAYOUT_ROWS 0
+#define SAQ_LAYOUT_DIMS 1
+
+/* The projection step alone (the GEMM saq_encode runs):
+   O = M (x_i - c) for the D_kept kept dims in the given layout, and
+   norm2_dev[i] = ||x_i - c||^2 (may be NULL). */
+saq_status saq_project(const saq_plan* plan, const float* X_dev, int64_t n,
+                       float* O_dev, int64_t ld, int32_t layout, float* norm2_dev,
+                       void* stream);
+
+/* Everything after the projection (the second kernel saq_encode runs), on
+   given projected rows O_dev in the given layout: quantization, adjustment,
+   factors and packing exactly as in saq_encode.  norm2_dev gives the last
+   factor (||x - c||^2); when NULL the squared norm of the kept dims is used. */
+saq_status saq_quantize(const saq_plan* plan, const float* O_dev, int64_t ld, int32_t layout,
+                        int64_t n, const float* norm2_dev, int32_t rounds, uint8_t* codes_dev,
+                        float* factors_dev, void* stream);
+
+/* Estimated squared distances (Section 3.2, Eq. estimator_inner_product)
+   between nq query rows Q_dev [nq x D] and n encoded records:
+     dist2_dev[q * n + i] = ||o_i||^2 + ||q - c||^2 - 2 sum_s f_s <u_s, q'_s>,
+   q' = M (q - c).  ws_dev: saq_estimate_workspace_bytes(plan, nq) bytes. */
+int64_t    saq_estimate_workspace_bytes(const saq_plan* plan, int32_t nq);
+saq_status saq_estimate_dist(const saq_plan* plan, const float* Q_dev, int32_t nq,
+                             const uint8_t* codes_dev, const float* factors_dev, int64_t n,
+                             float* dist2_dev, void* ws_dev, int64_t ws_bytes, void* stream);
+
+const char* saq_last_error(void);
+const char* saq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAQ_H */

@@ -1,0 +1,365 @@
+"""MI355X SAQ encoder: Python binding of libsaq.so (include/saq.h).
+
+Argument marshalling only: every step of the encode and estimate paths runs in
+the library's HIP kernels; PyTorch supplies device memory and streams.  If the
+library is missing this module raises instead of falling back to anything.
+
+SAQ: "Pushing the Limits of Vector Quantization through Code Adjustment and
+Dimension Segmentation" (SIGMOD'26, arXiv 2509.12086).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsaq.so")
+
+LAYOUT_ROWS = 0
+LAYOUT_DIMS = 1
+
+_STATUS = {0: "SAQ_OK", 1: "SAQ_EINVAL", 2: "SAQ_ENOMEM", 3: "SAQ_EDEVICE",
+           4: "SAQ_EUNSUPPORTED", 5: "SAQ_EIO"}
+
+
+class SaqError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("bits_per_dim", ctypes.c_double), ("granularity", ctypes.c_int32),
+                ("max_bits", ctypes.c_int32), ("max_width", ctypes.c_int32),
+                ("seg_eps", ctypes.c_double), ("rotate_segments", ctypes.c_int32),
+                ("fit_sample", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("D_kept", ctypes.c_int32), ("n_seg", ctypes.c_int32),
+                ("n_kept", ctypes.c_int32), ("code_bytes", ctypes.c_int64),
+                ("n_factors", ctypes.c_int32), ("max_kept_width", ctypes.c_int32),
+                ("max_kept_bits", ctypes.c_int32), ("model_error", ctypes.c_double),
+                ("min_error", ctypes.c_double), ("quota_bits", ctypes.c_int64),
+                ("used_bits", ctypes.c_int64)]
+
+
+_lib = None
+EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_plan_from_parts",
+           "saq_plan_info_get", "saq_plan_segments", "saq_plan_arrays", "saq_plan_save",
+           "saq_plan_load", "saq_plan_free", "saq_plan_device_bytes", "saq_plan_upload",
+           "saq_encode_workspace_bytes", "saq_encode", "saq_project", "saq_quantize",
+           "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_last_error", "saq_version")
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsaq.so (built in-tree by ``paper_2509_12086_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2509_12086_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "saq_default_params": (None, [ctypes.POINTER(_Params)]),
+        "saq_fit_plan": (i32, [P, i64, i32, ctypes.POINTER(_Params), pp]),
+        "saq_plan_from_basis": (i32, [P, P, P, i32, ctypes.POINTER(_Params), pp]),
+        "saq_plan_from_parts": (i32, [i32, i32, P, P, P, P, P, pp]),
+        "saq_plan_info_get": (i32, [P, ctypes.POINTER(_Info)]),
+        "saq_plan_segments": (i32, [P, P, P]),
+        "saq_plan_arrays": (i32, [P, P, P, P]),
+        "saq_plan_save": (i32, [P, ctypes.c_char_p]),
+        "saq_plan_load": (i32, [ctypes.c_char_p, pp]),
+        "saq_plan_free": (None, [P]),
+        "saq_plan_device_bytes": (i64, [P]),
+        "saq_plan_upload": (i32, [P, P, P]),
+        "saq_encode_workspace_bytes": (i64, [P, i64]),
+        "saq_encode": (i32, [P, P, i64, i32, P, P, P, i64, P]),
+        "saq_project": (i32, [P, P, i64, P, i64, i32, P, P]),
+        "saq_quantize": (i32, [P, P, i64, i32, i64, P, i32, P, P, P]),
+        "saq_estimate_workspace_bytes": (i64, [P, i32]),
+        "saq_estimate_dist": (i32, [P, P, i32, P, P, i64, P, P, i64, P]),
+        "saq_last_error": (ctypes.c_char_p, []),
+        "saq_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise SaqError(rc, lib().saq_last_error().decode())
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclasses.dataclass
+class PlanParams:
+    """Plan-search parameters (Sections 4.1-4.2); see saq_plan_params."""
+    bits_per_dim: float = 4.0
+    granularity: int = 16
+    max_bits: int = 9
+    max_width: int = 512
+    seg_eps: float = 1e-3
+    rotate_segments: bool = True
+    fit_sample: int = 65536
+    seed: int = 1
+
+    def _c(self) -> _Params:
+        return _Params(float(self.bits_per_dim), int(self.granularity), int(self.max_bits),
+                       int(self.max_width), float(self.seg_eps), int(bool(self.rotate_segments)),
+                       int(self.fit_sample), int(self.seed))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_ptr(stream, device=None):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A quantization plan: segments and bits, projection matrix M (FP32,
+    kept dims x D), reference vector c and per-dim variances."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+        self._dev = None                 # torch uint8 tensor holding the device copy
+        info = _Info()
+        _check(lib().saq_plan_info_get(self._h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _Info._fields_}
+        w = np.zeros(self.info["n_seg"], np.int32)
+        b = np.zeros(self.info["n_seg"], np.int32)
+        _check(lib().saq_plan_segments(self._h, _np_ptr(w), _np_ptr(b)))
+        self.widths, self.bits = w.tolist(), b.tolist()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.saq_plan_free(h)
+            self._h = None
+
+    # -- construction ------------------------------------------------------
+    @classmethod
+    def fit(cls, X: np.ndarray, params: Optional[PlanParams] = None) -> "Plan":
+        X = np.ascontiguousarray(X, np.float32)
+        p = (params or PlanParams())._c()
+        h = ctypes.c_void_p()
+        _check(lib().saq_fit_plan(_np_ptr(X), X.shape[0], X.shape[1], ctypes.byref(p),
+                                  ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_basis(cls, mean, eigvecs, eigvals, params: Optional[PlanParams] = None) -> "Plan":
+        mean = np.ascontiguousarray(mean, np.float64)
+        V = np.ascontiguousarray(eigvecs, np.float64)
+        lam = np.ascontiguousarray(eigvals, np.float64)
+        p = (params or PlanParams())._c()
+        h = ctypes.c_void_p()
+        _check(lib().saq_plan_from_basis(_np_ptr(mean), _np_ptr(V), _np_ptr(lam), mean.size,
+                                         ctypes.byref(p), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_parts(cls, widths: Sequence[int], bits: Sequence[int], M: np.ndarray, c: np.ndarray,
+                   variances: Optional[np.ndarray] = None) -> "Plan":
+        w = np.ascontiguousarray(widths, np.int32)
+        b = np.ascontiguousarray(bits, np.int32)
+        M = np.ascontiguousarray(M, np.float32)
+        c = np.ascontiguousarray(c, np.float32)
+        var = None if variances is None else np.ascontiguousarray(variances, np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().saq_plan_from_parts(c.size, w.size, _np_ptr(w), _np_ptr(b),
+                                         _np_ptr(M) if M.size else None, _np_ptr(c),
+                                         _np_ptr(var), ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def load(cls, path: str) -> "Plan":
+        h = ctypes.c_void_p()
+        _check(lib().saq_plan_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(h.value)
+
+    def save(self, path: str) -> None:
+        _check(lib().saq_plan_save(self._h, os.fsencode(path)))
+
+    # -- data ----------------------------------------------------------------
+    @property
+    def D(self) -> int:
+        return self.info["D"]
+
+    @property
+    def D_kept(self) -> int:
+        return self.info["D_kept"]
+
+    @property
+    def code_bytes(self) -> int:
+        return self.info["code_bytes"]
+
+    @property
+    def n_factors(self) -> int:
+        return self.info["n_factors"]
+
+    @property
+    def kept_widths(self):
+        return [w for w, b in zip(self.widths, self.bits) if b > 0]
+
+    @property
+    def kept_bits(self):
+        return [b for b in self.bits if b > 0]
+
+    def arrays(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        M = np.zeros((self.D_kept, self.D), np.float32)
+        c = np.zeros(self.D, np.float32)
+        var = np.zeros(self.D, np.float64)
+        _check(lib().saq_plan_arrays(self._h, _np_ptr(M) if M.size else None, _np_ptr(c),
+                                     _np_ptr(var)))
+        return M, c, var
+
+    # -- device --------------------------------------------------------------
+    def device_bytes(self) -> int:
+        return int(lib().saq_plan_device_bytes(self._h))
+
+    def upload(self, device=None, stream=None) -> "Plan":
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        buf = torch.empty(self.device_bytes() + 256, dtype=torch.uint8, device=dev)
+        off = (-buf.data_ptr()) % 256
+        with torch.cuda.device(dev):
+            _check(lib().saq_plan_upload(self._h, ctypes.c_void_p(buf.data_ptr() + off),
+                                         _stream_ptr(stream, dev)))
+        self._dev = buf
+        return self
+
+    def encode_workspace_bytes(self, n: int) -> int:
+        return int(lib().saq_encode_workspace_bytes(self._h, n))
+
+    def estimate_workspace_bytes(self, nq: int) -> int:
+        return int(lib().saq_estimate_workspace_bytes(self._h, nq))
+
+
+def _require_cuda_f32(t, name, cols=None):
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
+        raise TypeError(f"{name} must be a CUDA float32 tensor")
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D tensor")
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
+
+
+def _alloc_out(plan: Plan, n: int, device, codes=None, factors=None):
+    torch = _torch()
+    if codes is None:
+        codes = torch.empty((n, plan.code_bytes), dtype=torch.uint8, device=device)
+    if factors is None:
+        factors = torch.empty((n, plan.n_factors), dtype=torch.float32, device=device)
+    if codes.shape != (n, plan.code_bytes) or codes.dtype != torch.uint8 or not codes.is_contiguous():
+        raise ValueError("codes must be a contiguous uint8 tensor [n, code_bytes]")
+    if factors.shape != (n, plan.n_factors) or factors.dtype != torch.float32 or not factors.is_contiguous():
+        raise ValueError("factors must be a contiguous float32 tensor [n, n_factors]")
+    return codes, factors
+
+
+def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=None, stream=None):
+    """saq_encode: returns (codes uint8 [n, code_bytes], factors f32 [n, n_factors])."""
+    torch = _torch()
+    _require_cuda_f32(X, "X", plan.D)
+    n = X.shape[0]
+    codes, factors = _alloc_out(plan, n, X.device, codes, factors)
+    need = plan.encode_workspace_bytes(n)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _check(lib().saq_encode(plan._h, _dev_ptr(X), n, rounds, _dev_ptr(codes), _dev_ptr(factors),
+                            _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
+                            _stream_ptr(stream, X.device)))
+    return codes, factors
+
+
+def project(plan: Plan, X, out=None, norm2=None, layout: int = LAYOUT_ROWS, stream=None):
+    """saq_project: (O f32, ||x - c||^2 f32 [n]).  Row layout: O [n, >= D_kept];
+    dims layout: O [D_kept, ld >= n] with ld % 4 == 0."""
+    torch = _torch()
+    _require_cuda_f32(X, "X", plan.D)
+    n = X.shape[0]
+    if out is None:
+        shape = (n, max(plan.D_kept, 1)) if layout == LAYOUT_ROWS else \
+            (max(plan.D_kept, 1), (n + 3) // 4 * 4)
+        out = torch.empty(shape, dtype=torch.float32, device=X.device)
+    if norm2 is None:
+        norm2 = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check(lib().saq_project(plan._h, _dev_ptr(X), n, _dev_ptr(out), out.stride(0), layout,
+                             _dev_ptr(norm2), _stream_ptr(stream, X.device)))
+    return out, norm2
+
+
+def quantize(plan: Plan, O, rounds: int = 4, norm2=None, codes=None, factors=None,
+             layout: int = LAYOUT_ROWS, n: Optional[int] = None, stream=None):
+    """saq_quantize on projected rows O (row layout [n, >= D_kept], or dims
+    layout [D_kept, ld] with ``n`` given)."""
+    _require_cuda_f32(O, "O")
+    if n is None:
+        if layout != LAYOUT_ROWS:
+            raise ValueError("n is required for the dims layout")
+        n = O.shape[0]
+    codes, factors = _alloc_out(plan, n, O.device, codes, factors)
+    _check(lib().saq_quantize(plan._h, _dev_ptr(O), O.stride(0), layout, n, _dev_ptr(norm2),
+                              rounds, _dev_ptr(codes), _dev_ptr(factors),
+                              _stream_ptr(stream, O.device)))
+    return codes, factors
+
+
+def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, stream=None):
+    """saq_estimate_dist: estimated squared distances f32 [nq, n]."""
+    torch = _torch()
+    _require_cuda_f32(Q, "Q", plan.D)
+    nq, n = Q.shape[0], codes.shape[0]
+    if out is None:
+        out = torch.empty((nq, n), dtype=torch.float32, device=Q.device)
+    need = plan.estimate_workspace_bytes(nq)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=Q.device)
+    _check(lib().saq_estimate_dist(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes), _dev_ptr(factors), n,
+                                   _dev_ptr(out), _dev_ptr(workspace),
+                                   workspace.numel() * workspace.element_size(),
+                                   _stream_ptr(stream, Q.device)))
+    return out
+
+
+def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:
+    """Host-side decoding of records [n, code_bytes] into codes [n, D_kept]
+    (int32) following the bit-plane layout of include/saq.h."""
+    packed = np.asarray(packed, np.uint8)
+    n = packed.shape[0]
+    out = np.zeros((n, plan.D_kept), np.int32)
+    pos = off = 0
+    for w, b in zip(plan.kept_widths, plan.kept_bits):
+        pb = (w + 7) // 8
+        for p in range(b - 1, -1, -1):
+            bits = np.unpackbits(packed[:, pos:pos + pb], axis=1, bitorder="little")[:, :w]
+            out[:, off:off + w] |= bits.astype(np.int32) << p
+            pos += pb
+        off += w
+    return out

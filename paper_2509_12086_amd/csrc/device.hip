@@ -1,0 +1,574 @@
+// Device half of libsaq.so (gfx950): the SAQ encode hot path and the
+// estimate scan, plus their C-ABI entry points.
+//
+//   project_kernel   o = M (x - c) as an FP32 matrix-core GEMM
+//                    (v_mfma_f32_32x32x2_f32), centering fused into the
+//                    A-tile load, exact FP64 ||x - c||^2 on the side.
+//   quantize_kernel  per (vector, kept segment): v_max, the grid code of
+//                    Eq. (find_nearest_code), the code adjustment of
+//                    Algorithm 1 with FP64 decisions, the factor and the
+//                    bit-plane record.  One lane per vector, 64 vectors per
+//                    wave, all lanes on the same segment in lock step.
+//   estimate_kernel  Section 3.2 estimator over packed records.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "plan.hpp"
+
+using saq::SegEntry;
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int TM = saq::kGemmTileM;   // 128 vectors per tile
+constexpr int TN = saq::kGemmTileN;   // 128 kept dims per tile
+constexpr int TK = saq::kGemmTileK;   // 32 input dims per k-step
+constexpr int LDS_STRIDE = TK + 4;    // floats per LDS row (conflict-free b128 reads)
+constexpr int NXCD = 8;               // MI355X: 8 XCDs, workgroups dealt round-robin
+
+enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1 };
+
+// ---------------------------------------------------------------------------
+// Projection GEMM.  Workgroup = 256 threads (4 waves) computes a 128 x 128
+// tile of O (vectors x kept dims); each wave a 64 x 64 quarter as 2 x 2
+// 32x32 MFMA blocks.  The 32-wide k-step is split between the two half-waves:
+// half h feeds k = 16h + j at MFMA step j, so every lane reads 16 contiguous
+// floats per row from LDS (4 x ds_read_b128).
+//
+// Tile order is XCD-aware: workgroup b runs on XCD b % 8; XCD x walks row
+// tiles x, x+8, ... and, inside each, all column tiles back to back, so the
+// X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
+// ---------------------------------------------------------------------------
+template <bool VEC, int LAYOUT>
+__global__ __launch_bounds__(256) void project_kernel(
+    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
+    const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(16))) float As[2][TM * LDS_STRIDE];
+    __shared__ __attribute__((aligned(16))) float Bs[2][TN * LDS_STRIDE];
+
+    const int bid = blockIdx.x;
+    const int xcd = bid % NXCD, local = bid / NXCD;
+    const int tile_n = local % tiles_n;
+    const int tile_m = (local / tiles_n) * NXCD + xcd;
+    if (tile_m >= tiles_m) return;
+    const int64_t m0 = int64_t(tile_m) * TM;
+    const int n0 = tile_n * TN;
+
+    const int t = threadIdx.x;
+    const int lr = t >> 1;              // row loaded by this thread (A and B)
+    const int lk = (t & 1) * 16;        // k offset inside the tile
+    const int64_t arow = m0 + lr;
+    const bool arow_ok = arow < n;
+    const float* xrow = X + (arow_ok ? arow : 0) * int64_t(D);
+    const float* brow = Mp + int64_t(n0 + lr) * k_pad;
+    const bool do_norm = (norm2 != nullptr) && tile_n == 0;
+    double nacc = 0.0;
+
+    float ra[16], rb[16];
+    auto load_tile = [&](int k0) {
+        const int kb = k0 + lk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 c4 = *reinterpret_cast<const float4*>(cp + kb + 4 * q);
+            float4 x4;
+            if (VEC) {
+                if (arow_ok && kb + 4 * q + 4 <= D) {
+                    x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
+                } else {
+                    x4.x = (arow_ok && kb + 4 * q + 0 < D) ? xrow[kb + 4 * q + 0] : 0.f;
+                    x4.y = (arow_ok && kb + 4 * q + 1 < D) ? xrow[kb + 4 * q + 1] : 0.f;
+                    x4.z = (arow_ok && kb + 4 * q + 2 < D) ? xrow[kb + 4 * q + 2] : 0.f;
+                    x4.w = (arow_ok && kb + 4 * q + 3 < D) ? xrow[kb + 4 * q + 3] : 0.f;
+                }
+            } else {
+                x4.x = (arow_ok && kb + 4 * q + 0 < D) ? xrow[kb + 4 * q + 0] : 0.f;
+                x4.y = (arow_ok && kb + 4 * q + 1 < D) ? xrow[kb + 4 * q + 1] : 0.f;
+                x4.z = (arow_ok && kb + 4 * q + 2 < D) ? xrow[kb + 4 * q + 2] : 0.f;
+                x4.w = (arow_ok && kb + 4 * q + 3 < D) ? xrow[kb + 4 * q + 3] : 0.f;
+            }
+            if (do_norm) {
+                // exact (x - c)^2 in FP64; padding entries are 0 - 0
+                double d0 = double(x4.x) - double(c4.x), d1 = double(x4.y) - double(c4.y);
+                double d2 = double(x4.z) - double(c4.z), d3 = double(x4.w) - double(c4.w);
+                nacc = fma(d0, d0, nacc); nacc = fma(d1, d1, nacc);
+                nacc = fma(d2, d2, nacc); nacc = fma(d3, d3, nacc);
+            }
+            ra[4 * q + 0] = x4.x - c4.x; ra[4 * q + 1] = x4.y - c4.y;
+            ra[4 * q + 2] = x4.z - c4.z; ra[4 * q + 3] = x4.w - c4.w;
+            const float4 b4 = *reinterpret_cast<const float4*>(brow + kb + 4 * q);
+            rb[4 * q + 0] = b4.x; rb[4 * q + 1] = b4.y; rb[4 * q + 2] = b4.z; rb[4 * q + 3] = b4.w;
+        }
+    };
+    auto store_tile = [&](int buf) {
+        float* a = &As[buf][lr * LDS_STRIDE + lk];
+        float* b = &Bs[buf][lr * LDS_STRIDE + lk];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            *reinterpret_cast<float4*>(a + 4 * q) = make_float4(ra[4 * q], ra[4 * q + 1], ra[4 * q + 2], ra[4 * q + 3]);
+            *reinterpret_cast<float4*>(b + 4 * q) = make_float4(rb[4 * q], rb[4 * q + 1], rb[4 * q + 2], rb[4 * q + 3]);
+        }
+    };
+
+    const int wave = t >> 6, lane = t & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 31, lh = lane >> 5;
+    floatx16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    const int ktiles = k_pad / TK;
+    load_tile(0);
+    store_tile(0);
+    __syncthreads();
+    for (int kt = 0; kt < ktiles; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < ktiles) load_tile((kt + 1) * TK);
+        const float* a0 = &As[buf][(wm * 64 + li) * LDS_STRIDE + lh * 16];
+        const float* a1 = a0 + 32 * LDS_STRIDE;
+        const float* b0 = &Bs[buf][(wn * 64 + li) * LDS_STRIDE + lh * 16];
+        const float* b1 = b0 + 32 * LDS_STRIDE;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 va0 = *reinterpret_cast<const float4*>(a0 + 4 * q);
+            const float4 va1 = *reinterpret_cast<const float4*>(a1 + 4 * q);
+            const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
+            const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
+            const float A0[4] = {va0.x, va0.y, va0.z, va0.w};
+            const float A1[4] = {va1.x, va1.y, va1.z, va1.w};
+            const float B0[4] = {vb0.x, vb0.y, vb0.z, vb0.w};
+            const float B1[4] = {vb1.x, vb1.y, vb1.z, vb1.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B0[j], acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B1[j], acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B0[j], acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B1[j], acc[1][1], 0, 0, 0);
+            }
+        }
+        if (kt + 1 < ktiles) store_tile(buf ^ 1);
+        __syncthreads();
+    }
+
+    if (do_norm) {
+        nacc += __shfl_xor(nacc, 1);
+        if ((t & 1) == 0 && arow_ok) norm2[arow] = float(nacc);
+    }
+
+    // epilogue: lane holds column n0 + wn*64 + 32*bj + li and, for register
+    // r, row m0 + wm*64 + 32*bi + 8*(r/4) + 4*lh + r%4
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = n0 + wn * 64 + bj * 32 + li;
+            if (col >= dk) continue;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t row = m0 + wm * 64 + bi * 32 + 8 * g + 4 * lh;
+                const float v0 = acc[bi][bj][4 * g + 0], v1 = acc[bi][bj][4 * g + 1];
+                const float v2 = acc[bi][bj][4 * g + 2], v3 = acc[bi][bj][4 * g + 3];
+                if (LAYOUT == LAYOUT_DIMS) {
+                    float* dst = O + int64_t(col) * ld + row;
+                    if (row + 3 < n) {
+                        *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+                    } else {
+                        if (row + 0 < n) dst[0] = v0;
+                        if (row + 1 < n) dst[1] = v1;
+                        if (row + 2 < n) dst[2] = v2;
+                        if (row + 3 < n) dst[3] = v3;
+                    }
+                } else {
+                    if (row + 0 < n) O[(row + 0) * ld + col] = v0;
+                    if (row + 1 < n) O[(row + 1) * ld + col] = v1;
+                    if (row + 2 < n) O[(row + 2) * ld + col] = v2;
+                    if (row + 3 < n) O[(row + 3) * ld + col] = v3;
+                }
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Quantize + adjust + factor + pack.  One wave (64 lanes) per block, one
+// vector per lane; the block's 64 codes of the current segment live in LDS
+// as [dim][lane] (conflict-free), the projected values stream from O.
+//
+// Adjustment decision (Algorithm 1, "L(x') > L(x)"), exact reformulation:
+// with u = code - (2^B-1)/2, ip = <u,o>, n = ||u||^2 and a move u_i += s,
+// L' > L  <=>  ip'^2 n > ip^2 n'  (given ip' > 0, which holds for every move
+// that passes this test because each term u_j o_j >= 0), i.e.
+//   s = +1:  n o (2 ip + o) > ip^2 (2u + 1)
+//   s = -1:  n o (o - 2 ip) > ip^2 (1 - 2u)
+// evaluated in FP64 (o is FP32, so these are within a few ulps of exact).
+// +1 is tried first; after an accepted +1 the reverting -1 can never pass.
+// A round that accepts nothing leaves the state unchanged, so once no lane
+// of the wave accepted anything the remaining rounds are skipped.
+// ---------------------------------------------------------------------------
+template <typename CT, int LAYOUT>
+__global__ __launch_bounds__(64) void quantize_kernel(
+    const float* __restrict__ O, int64_t ld, int64_t n, const SegEntry* __restrict__ segs,
+    int n_kept, const float* __restrict__ norm2, int rounds, uint8_t* __restrict__ codes,
+    int64_t code_bytes, float* __restrict__ factors) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    CT* lc = reinterpret_cast<CT*>(smem);
+    const int lane = threadIdx.x;
+    const int64_t v = int64_t(blockIdx.x) * 64 + lane;
+    const bool live = v < n;
+    const int64_t vv = live ? v : n - 1;
+    // element (vector vv, kept dim j)
+    const int64_t sv = LAYOUT == LAYOUT_DIMS ? 1 : ld;
+    const int64_t sd = LAYOUT == LAYOUT_DIMS ? ld : 1;
+    const float* ov = O + vv * sv;
+    uint8_t* rec = codes + vv * code_bytes;
+    double kept_norm = 0.0;
+
+    for (int s = 0; s < n_kept; ++s) {
+        const SegEntry e = segs[s];
+        const int W = e.width, B = e.bits;
+        const int cmax = (1 << B) - 1;
+        const float* os = ov + int64_t(e.col) * sd;
+
+        // v_max = max |o_i| (exact in FP32) and ||o_s||^2 (FP64)
+        float vmax = 0.f;
+        double oo = 0.0;
+        for (int i = 0; i < W; ++i) {
+            const float o = os[i * sd];
+            vmax = fmaxf(vmax, fabsf(o));
+            oo = fma(double(o), double(o), oo);
+        }
+        kept_norm += oo;
+        const bool zero = !(vmax > 0.f);
+
+        // initial code: c = floor((o + v) / Delta), Delta = 2 v / 2^B, clamped
+        // to 2^B - 1; computed as the exact floor (o + v and k * Delta are
+        // exact in FP64)
+        const double vd = double(vmax);
+        const double delta = zero ? 1.0 : ldexp(2.0 * vd, -B);
+        const double inv = 1.0 / delta;
+        const double half = 0.5 * double(cmax);
+        double ip = 0.0, nn = 0.0;
+        for (int i = 0; i < W; ++i) {
+            const double o = double(os[i * sd]);
+            int c;
+            if (zero) {
+                c = (cmax + 1) >> 1;
+            } else {
+                const double a = o + vd;
+                double q = floor(a * inv);
+                if ((q + 1.0) * delta <= a) q += 1.0;
+                if (q * delta > a) q -= 1.0;
+                q = fmin(fmax(q, 0.0), double(cmax));
+                c = int(q);
+            }
+            lc[i * 64 + lane] = CT(c);
+            const double u = double(c) - half;
+            ip = fma(u, o, ip);
+            nn = fma(u, u, nn);
+        }
+
+        if (B >= 2 && rounds > 0) {
+            double P = 2.0 * ip, S = ip * ip;
+            for (int rd = 0; rd < rounds; ++rd) {
+                int moved = 0;
+                for (int i = 0; i < W; ++i) {
+                    const double o = double(os[i * sd]);
+                    const int c = int(lc[i * 64 + lane]);
+                    const double w = double(2 * c - cmax);          // 2u
+                    const double no = nn * o;
+                    const double Lp = no * (P + o), Rp = fma(S, w, S);
+                    const double Lm = no * (o - P), Rm = fma(-S, w, S);
+                    const bool up = !zero && c < cmax && Lp > Rp;
+                    const bool dn = !zero && !up && c > 0 && Lm > Rm;
+                    if (up || dn) {
+                        const double sg = up ? 1.0 : -1.0;
+                        nn = nn + fma(sg, w, 1.0);      // (u + s)^2 = u^2 + 2su + 1
+                        ip = fma(sg, o, ip);
+                        P = 2.0 * ip;
+                        S = ip * ip;
+                        lc[i * 64 + lane] = CT(c + (up ? 1 : -1));
+                        moved = 1;
+                    }
+                }
+                if (!__any(moved)) break;
+            }
+        }
+
+        // factor f_s = ||o_s||^2 / <u_s, o_s>
+        if (live) factors[v * (n_kept + 1) + s] = zero ? 0.f : float(oo / ip);
+
+        // bit planes, most significant first; dim i -> byte i/8, bit i%8
+        const int pb = (W + 7) >> 3;
+        for (int j = 0; j < pb; ++j) {
+            int cc[8];
+#pragma unroll
+            for (int t2 = 0; t2 < 8; ++t2) {
+                const int i = 8 * j + t2;
+                cc[t2] = i < W ? int(lc[i * 64 + lane]) : 0;
+            }
+            for (int p = B - 1; p >= 0; --p) {
+                unsigned byte = 0;
+#pragma unroll
+                for (int t2 = 0; t2 < 8; ++t2) byte |= unsigned((cc[t2] >> p) & 1) << t2;
+                if (live) rec[e.code_off + int64_t(B - 1 - p) * pb + j] = uint8_t(byte);
+            }
+        }
+    }
+    if (live) factors[v * (n_kept + 1) + n_kept] = norm2 ? norm2[v] : float(kept_norm);
+}
+
+// ---------------------------------------------------------------------------
+// Estimate scan: one thread per stored record, QG queries per block.  For
+// each kept segment the projected queries' slice is staged in LDS; the
+// record's bit planes are decoded 8 dims at a time into u = code - (2^B-1)/2
+// and dotted with every staged query; the segment sum is scaled by f_s.
+// ---------------------------------------------------------------------------
+constexpr int QG = 16;
+
+__global__ __launch_bounds__(256) void estimate_kernel(
+    const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
+    const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
+    int64_t code_bytes, const float* __restrict__ factors, int64_t n,
+    float* __restrict__ out, int max_w) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    float* qs = reinterpret_cast<float*>(smem);     // [QG][max_w]
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int q0 = blockIdx.y * QG;
+    const int nqg = min(QG, nq - q0);
+    const bool live = i < n;
+    const int64_t ii = live ? i : n - 1;
+    const uint8_t* rec = codes + ii * code_bytes;
+    const float* f = factors + ii * (n_kept + 1);
+    float acc[QG];
+#pragma unroll
+    for (int q = 0; q < QG; ++q) acc[q] = 0.f;
+    for (int s = 0; s < n_kept; ++s) {
+        const SegEntry e = segs[s];
+        const int W = e.width, B = e.bits, pb = (W + 7) >> 3;
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < QG * W; idx += blockDim.x) {
+            const int q = idx / W, j = idx - q * W;
+            qs[q * max_w + j] = q < nqg ? Qp[int64_t(q0 + q) * dk + e.col + j] : 0.f;
+        }
+        __syncthreads();
+        const float h = 0.5f * float((1 << B) - 1);
+        float sacc[QG];
+#pragma unroll
+        for (int q = 0; q < QG; ++q) sacc[q] = 0.f;
+        for (int j = 0; j < pb; ++j) {
+            int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int p = 0; p < B; ++p) {
+                const unsigned byte = rec[e.code_off + int64_t(p) * pb + j];
+#pragma unroll
+                for (int t2 = 0; t2 < 8; ++t2) c[t2] = (c[t2] << 1) | int((byte >> t2) & 1u);
+            }
+            float u[8];
+#pragma unroll
+            for (int t2 = 0; t2 < 8; ++t2) u[t2] = (8 * j + t2 < W) ? float(c[t2]) - h : 0.f;
+#pragma unroll
+            for (int q = 0; q < QG; ++q) {
+                const float* qq = qs + q * max_w + 8 * j;
+                float a = sacc[q];
+#pragma unroll
+                for (int t2 = 0; t2 < 8; ++t2)
+                    if (8 * j + t2 < W) a = fmaf(u[t2], qq[t2], a);
+                sacc[q] = a;
+            }
+        }
+        const float fs = f[s];
+#pragma unroll
+        for (int q = 0; q < QG; ++q) acc[q] = fmaf(fs, sacc[q], acc[q]);
+    }
+    if (!live) return;
+    const float on = f[n_kept];
+    for (int q = 0; q < nqg; ++q) out[int64_t(q0 + q) * n + i] = on + qn2[q0 + q] - 2.f * acc[q];
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+saq_status hip_fail(hipError_t e, const char* what) {
+    return saq::fail(SAQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool uploaded(const saq_plan* p) { return p && p->dev != nullptr; }
+
+const float* dev_M(const saq_plan* p) {
+    return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_M);
+}
+const float* dev_c(const saq_plan* p) {
+    return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_c);
+}
+const SegEntry* dev_seg(const saq_plan* p) {
+    return reinterpret_cast<const SegEntry*>(static_cast<const char*>(p->dev) + p->layout.off_seg);
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O, int64_t ld,
+                          int layout, float* norm2, hipStream_t st) {
+    const int tiles_m = int((n + TM - 1) / TM);
+    const int tiles_n = p->layout.n_pad / TN;
+    const int slots = (tiles_m + NXCD - 1) / NXCD;
+    const dim3 grid(unsigned(NXCD * slots * tiles_n));
+    const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+    if (layout == LAYOUT_DIMS && ((reinterpret_cast<uintptr_t>(O) & 15) != 0 || (ld % 4) != 0))
+        return saq::fail(SAQ_EINVAL, "dims-major output needs a 16-byte aligned buffer and ld % 4 == 0");
+#define SAQ_LAUNCH_PROJ(V, L)                                                                     \
+    hipLaunchKernelGGL((project_kernel<V, L>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),      \
+                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n)
+    if (layout == LAYOUT_DIMS) {
+        if (vec) SAQ_LAUNCH_PROJ(true, LAYOUT_DIMS); else SAQ_LAUNCH_PROJ(false, LAYOUT_DIMS);
+    } else {
+        if (vec) SAQ_LAUNCH_PROJ(true, LAYOUT_ROWS); else SAQ_LAUNCH_PROJ(false, LAYOUT_ROWS);
+    }
+#undef SAQ_LAUNCH_PROJ
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_fail(e, "project_kernel launch");
+}
+
+constexpr size_t kMaxDynLds = 65536;
+
+saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int layout, int64_t n,
+                           const float* norm2, int rounds, uint8_t* codes, float* factors,
+                           hipStream_t st) {
+    const bool small = p->max_kept_b <= 8;
+    const size_t lds = size_t(std::max(p->max_kept_w, 1)) * 64 * (small ? 1 : 2);
+    if (lds > kMaxDynLds)
+        return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the quantize kernel's "
+                                           "LDS code buffer (1024 dims at <= 8 bits, 512 above)");
+    const dim3 grid(unsigned((n + 63) / 64));
+#define SAQ_LAUNCH_Q(CT, L)                                                                       \
+    hipLaunchKernelGGL((quantize_kernel<CT, L>), grid, dim3(64), lds, st, O, ld, n, dev_seg(p),   \
+                       p->n_kept, norm2, rounds, codes, p->code_bytes, factors)
+    if (layout == LAYOUT_DIMS) {
+        if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_DIMS); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_DIMS);
+    } else {
+        if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_ROWS); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_ROWS);
+    }
+#undef SAQ_LAUNCH_Q
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_fail(e, "quantize_kernel launch");
+}
+
+// workspace of saq_encode: O (dims-major, [D_kept x ld]) then norm2 [n]
+int64_t enc_ld(int64_t n) { return round_up(std::max<int64_t>(n, 1), 4); }
+
+}  // namespace
+
+extern "C" {
+
+int64_t saq_plan_device_bytes(const saq_plan* p) { return p ? p->layout.bytes : -1; }
+
+saq_status saq_plan_upload(saq_plan* p, void* dev_buf, void* stream) {
+    if (!p || !dev_buf) return saq::fail(SAQ_EINVAL, "bad arguments");
+    if ((reinterpret_cast<uintptr_t>(dev_buf) & 255) != 0)
+        return saq::fail(SAQ_EINVAL, "plan buffer must be 256-byte aligned");
+    const hipError_t e = hipMemcpyAsync(dev_buf, p->staging.data(), size_t(p->layout.bytes),
+                                        hipMemcpyHostToDevice, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "plan upload");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    p->dev = dev_buf;
+    p->dev_id = dev;
+    return SAQ_OK;
+}
+
+int64_t saq_encode_workspace_bytes(const saq_plan* p, int64_t n) {
+    if (!p || n < 0) return -1;
+    return int64_t(p->D_kept) * enc_ld(n) * 4 + round_up(std::max<int64_t>(n, 1), 64) * 4 + 256;
+}
+
+static saq_status check_layout(const saq_plan* p, int64_t n, int64_t ld, int32_t layout) {
+    if (layout == LAYOUT_ROWS) {
+        if (ld < p->D_kept) return saq::fail(SAQ_EINVAL, "ld < D_kept for the row layout");
+    } else if (layout == LAYOUT_DIMS) {
+        if (ld < n || (ld % 4) != 0) return saq::fail(SAQ_EINVAL, "dims layout needs ld >= n and ld % 4 == 0");
+    } else {
+        return saq::fail(SAQ_EINVAL, "unknown layout");
+    }
+    return SAQ_OK;
+}
+
+saq_status saq_project(const saq_plan* p, const float* X, int64_t n, float* O, int64_t ld,
+                       int32_t layout, float* norm2, void* stream) {
+    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (n == 0) return SAQ_OK;
+    if (saq_status s = check_layout(p, n, ld, layout); s != SAQ_OK) return s;
+    if (!X || (!O && p->D_kept > 0)) return saq::fail(SAQ_EINVAL, "null buffer");
+    return launch_project(p, X, n, O, ld, layout, norm2, static_cast<hipStream_t>(stream));
+}
+
+saq_status saq_quantize(const saq_plan* p, const float* O, int64_t ld, int32_t layout, int64_t n,
+                        const float* norm2, int32_t rounds, uint8_t* codes, float* factors,
+                        void* stream) {
+    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (n == 0) return SAQ_OK;
+    if (saq_status s = check_layout(p, n, ld, layout); s != SAQ_OK) return s;
+    if ((!O && p->D_kept > 0) || !codes || !factors) return saq::fail(SAQ_EINVAL, "null buffer");
+    return launch_quantize(p, O, ld, layout, n, norm2, rounds, codes, factors,
+                           static_cast<hipStream_t>(stream));
+}
+
+saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
+                      uint8_t* codes, float* factors, void* ws, int64_t ws_bytes, void* stream) {
+    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (n == 0) return SAQ_OK;
+    if (!X || !codes || !factors || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
+    if (ws_bytes < saq_encode_workspace_bytes(p, n)) return saq::fail(SAQ_EINVAL, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t ld = enc_ld(n);
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    float* O = reinterpret_cast<float*>(base);
+    float* nrm = reinterpret_cast<float*>(base + int64_t(p->D_kept) * ld * 4);
+    // with nothing kept the projection kernel still runs its first column
+    // tile (all padding) to produce ||x - c||^2
+    saq_status s = launch_project(p, X, n, O, ld, LAYOUT_DIMS, nrm, st);
+    if (s != SAQ_OK) return s;
+    return launch_quantize(p, O, ld, LAYOUT_DIMS, n, nrm, rounds, codes, factors, st);
+}
+
+int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
+    if (!p || nq < 0) return -1;
+    return int64_t(std::max(nq, 1)) * std::max(p->D_kept, 1) * 4 + int64_t(std::max(nq, 1)) * 4 + 512;
+}
+
+saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, const uint8_t* codes,
+                             const float* factors, int64_t n, float* out, void* ws,
+                             int64_t ws_bytes, void* stream) {
+    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (nq == 0 || n == 0) return SAQ_OK;
+    if (!Q || !codes || !factors || !out || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
+    if (ws_bytes < saq_estimate_workspace_bytes(p, nq)) return saq::fail(SAQ_EINVAL, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    float* Qp = reinterpret_cast<float*>(base);
+    float* qn2 = Qp + int64_t(nq) * std::max(p->D_kept, 1);
+    saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st);
+    if (s != SAQ_OK) return s;
+    const int maxw = std::max(p->max_kept_w, 1);
+    if (size_t(QG) * maxw * 4 > kMaxDynLds)
+        return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the estimate kernel's "
+                                           "LDS query buffer (1024 dims)");
+    const dim3 grid(unsigned((n + 255) / 256), unsigned((nq + QG - 1) / QG));
+    hipLaunchKernelGGL(estimate_kernel, grid, dim3(256), size_t(QG) * maxw * 4, st, Qp, nq,
+                       std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
+                       factors, n, out, maxw);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
+}
+
+}  // extern "C"

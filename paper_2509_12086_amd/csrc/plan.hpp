@@ -1,0 +1,64 @@
+// Internal plan object shared by the host (fit, serialisation) and device
+// (upload, launches) halves of libsaq.so.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/saq.h"
+
+namespace saq {
+
+// Device plan layout (one caller-owned buffer, every region 256-byte aligned):
+//   M_pad   float [n_pad x k_pad]   rows = kept dims in plan order, zero padded
+//   c_pad   float [k_pad]
+//   segtab  int32 [n_kept x 4]      column start, width, bits, code byte offset
+constexpr int kGemmTileN = 128;   // GEMM tile along the kept dims
+constexpr int kGemmTileK = 32;    // GEMM tile along the input dims
+constexpr int kGemmTileM = 128;   // GEMM tile along the vectors
+
+struct SegEntry {
+    int32_t col;      // first kept column
+    int32_t width;    // W
+    int32_t bits;     // B (> 0)
+    int32_t code_off; // byte offset of the segment's first plane in a record
+};
+
+struct DeviceLayout {
+    int32_t n_pad = 0, k_pad = 0;
+    int64_t off_M = 0, off_c = 0, off_seg = 0, bytes = 0;
+};
+
+}  // namespace saq
+
+struct saq_plan {
+    int32_t D = 0;
+    std::vector<int32_t> widths, bits;   // all segments, plan order
+    std::vector<float> M;                // D_kept x D
+    std::vector<float> c;                // D
+    std::vector<double> var;             // D (variances sorted descending), zeros if unknown
+    saq_plan_params params{};
+    double model_error = 0.0, min_error = 0.0;
+    int64_t quota = 0, used = 0;
+
+    // derived
+    int32_t D_kept = 0, n_kept = 0, max_kept_w = 0, max_kept_b = 0;
+    int64_t code_bytes = 0;
+    std::vector<saq::SegEntry> kept;
+
+    // device copy
+    saq::DeviceLayout layout;
+    std::vector<unsigned char> staging;  // host image of the device buffer
+    void* dev = nullptr;                 // last upload target (caller-owned)
+    int dev_id = -1;
+
+    void derive();                       // fills the derived fields
+};
+
+namespace saq {
+void set_error(const std::string& msg);
+saq_status fail(saq_status st, const std::string& msg);
+DeviceLayout device_layout(const saq_plan& p);
+void build_staging(saq_plan& p);
+}  // namespace saq

@@ -1,0 +1,212 @@
+"""Device path vs the FP64 oracle, through the C ABI (libsaq.so).
+
+Tolerances (the benchmark spec): >= 99.99 % identical codes with every difference
+exactly 1, rescale factors within 1e-5 relative, mean relative distance
+error within 1 % of the oracle's.  The projection is an FP32 GEMM, so its
+elementwise error bound is the classical K u sum|x_k m_k| <= K u ||x - c||
+(u = 2^-24, ||m_j|| = 1)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2509_12086_amd as saq
+from gpu_util import compare, cuda, gpu_encode, oracle_encode, say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    ds = synth.cfg1()
+    X = ds.rows()
+    plan = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=4.0, fit_sample=0, seed=7)).upload(0)
+    return ds, X, plan
+
+
+def test_projection_fp32_mfma(cfg1):
+    ds, X, plan = cfg1
+    for n, D in [(10_000, 128), (1, 128), (129, 128), (1000, 100), (333, 99)]:
+        say(f"projection n={n} D={D}")
+        if D == 128:
+            p, Xs = plan, X[:n]
+        else:
+            Xs = np.random.default_rng(D).standard_normal((n, D)).astype(np.float32) * 2 + 1
+            p = saq.Plan.fit(Xs, saq.PlanParams(bits_per_dim=3.0, fit_sample=0)).upload(0)
+        M, c, _ = p.arrays()
+        O, nn = saq.project(p, to_dev(Xs))
+        Od, _ = saq.project(p, to_dev(Xs), layout=saq.LAYOUT_DIMS)
+        torch.cuda.synchronize()
+        O, nn, Od = O.cpu().numpy(), nn.cpu().numpy(), Od.cpu().numpy()
+        ref, nref = oracle.project(Xs, M, c)
+        err = np.abs(O[:, :p.D_kept] - ref)
+        xn = np.sqrt(nref)[:, None]
+        assert np.all(err <= D * U32 * xn * 1.01 + 1e-30)
+        assert np.sqrt(np.mean(err ** 2)) <= 4 * U32 * np.sqrt(np.mean(nref))
+        assert np.allclose(nn, nref, rtol=1e-6, atol=0)
+        # both output layouts come from the same accumulators
+        assert np.array_equal(Od[:p.D_kept, :n].T, O[:, :p.D_kept])
+
+
+def test_quantize_projected_input_matches_exactly(cfg1):
+    """Projected-input mode isolates the quantize/adjust/pack kernel: both
+    sides start from the same FP32 projected values."""
+    ds, X, plan = cfg1
+    M, c, _ = plan.arrays()
+    O64, nn = oracle.project(X, M, c)
+    O32 = O64.astype(np.float32)
+    for rounds in (0, 1, 4, 16):
+        say(f"projected-input cfg1 rounds={rounds}")
+        ref = oracle.quantize(O32.astype(np.float64), plan.kept_widths, plan.kept_bits, rounds)
+        ref.norm2 = nn
+        codes, fac = saq.quantize(plan, to_dev(O32), rounds, norm2=to_dev(nn.astype(np.float32)))
+        torch.cuda.synchronize()
+        rate = compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, max_rate=1e-6,
+                       label=f"proj r={rounds}")
+        assert rate == 0.0
+
+
+def test_quantize_projected_wide_bit_range():
+    """Segments from 1 to 16 bits (uint16 code storage) and a 0-bit tail."""
+    D = 160
+    widths, bits = [16, 48, 32, 16, 16, 32], [16, 9, 5, 2, 1, 0]
+    M = np.eye(D, dtype=np.float32)[:128]
+    plan = saq.Plan.from_parts(widths, bits, M, np.zeros(D, np.float32)).upload(0)
+    rng = np.random.default_rng(3)
+    O = (rng.standard_normal((777, 128)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3], [16, 48, 32, 16, 16])
+         ).astype(np.float32)
+    O[5] = 0.0                               # all-zero segments
+    O[6, :16] = 0.0
+    O[7, 16:64] = 3.0                        # ties at +v_max
+    for rounds in (0, 4):
+        say(f"projected-input wide bits rounds={rounds}")
+        ref = oracle.quantize(O.astype(np.float64), plan.kept_widths, plan.kept_bits, rounds)
+        ref.norm2 = (O.astype(np.float64) ** 2).sum(1)
+        codes, fac = saq.quantize(plan, to_dev(O), rounds)
+        torch.cuda.synchronize()
+        assert compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, max_rate=0,
+                       label=f"wide r={rounds}") == 0.0
+
+
+def test_encode_cfg1_end_to_end(cfg1):
+    ds, X, plan = cfg1
+    say("encode cfg1 10000 x 128, 4 b/dim, r=4")
+    packed, fac = gpu_encode(plan, X, 4)
+    ref = oracle_encode(plan, X, 4)
+    compare(plan, packed, fac, ref, label="cfg1")
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 127, 129, 1000])
+def test_encode_ragged_sizes(cfg1, n):
+    ds, X, plan = cfg1
+    say(f"encode ragged n={n}")
+    Xs = X[1000:1000 + n]
+    packed, fac = gpu_encode(plan, Xs, 4)
+    compare(plan, packed, fac, oracle_encode(plan, Xs, 4), label=f"n={n}")
+    # the records of a slice equal the rows of a bigger batch (no cross-talk)
+    big, bigf = gpu_encode(plan, X[990:1000 + n + 10], 4)
+    assert np.array_equal(big[10:10 + n], packed) and np.array_equal(bigf[10:10 + n], fac)
+
+
+def test_encode_degenerate_rows(cfg1):
+    ds, X, plan = cfg1
+    M, c, _ = plan.arrays()
+    Xs = X[:200].copy()
+    Xs[0] = c                       # o = 0: every segment has v_max = 0
+    Xs[1] = Xs[2]                   # duplicates
+    Xs[3] = c + 1e-3 * (X[3] - c)   # tiny vector
+    say("encode degenerate rows")
+    packed, fac = gpu_encode(plan, Xs, 4)
+    ref = oracle_encode(plan, Xs, 4)
+    compare(plan, packed, fac, ref, label="degenerate")
+    codes = saq.unpack_codes(plan, packed)
+    assert np.all(fac[0, :-1] == 0.0)
+    assert np.array_equal(packed[1], packed[2])
+
+
+def test_encode_non_multiple_dims_and_rounds():
+    """D = 99 (no 16-byte vector loads, ragged k tile) and several round limits."""
+    rng = np.random.default_rng(99)
+    lam = np.exp(-np.arange(99) / 20.0)
+    X = ((rng.standard_normal((2000, 99)) * np.sqrt(lam)) @ synth.haar_rotation(99, 4).T
+         ).astype(np.float32)
+    plan = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=2.5, granularity=8, max_width=32,
+                                          fit_sample=0)).upload(0)
+    for rounds in (0, 1, 8):
+        say(f"encode D=99 rounds={rounds}")
+        packed, fac = gpu_encode(plan, X, rounds)
+        compare(plan, packed, fac, oracle_encode(plan, X, rounds), label=f"D99 r={rounds}")
+
+
+def test_encode_deterministic(cfg1):
+    ds, X, plan = cfg1
+    a = gpu_encode(plan, X[:3000], 4)
+    b = gpu_encode(plan, X[:3000], 4)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_estimate_dist(cfg1):
+    """saq_estimate_dist equals the oracle's estimator evaluated on the same
+    records (FP32 accumulation tolerance), and the relative distance error of
+    the device-encoded records is within 1 % of the oracle-encoded ones'."""
+    ds, X, plan = cfg1
+    Qr = ds.queries(64)
+    Xs = X[:4000]
+    packed, fac = gpu_encode(plan, Xs, 4)
+    say("estimate cfg1 64 queries x 4000 records")
+    d2 = saq.estimate_dist(plan, to_dev(Qr), to_dev(packed), to_dev(fac))
+    torch.cuda.synchronize()
+    d2 = d2.cpu().numpy()
+    M, c, _ = plan.arrays()
+    codes = saq.unpack_codes(plan, packed)
+    ref = oracle.estimate(Qr, M, c, plan.kept_widths, plan.kept_bits, codes,
+                          fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
+    scale = fac[:, -1][None, :] + ((Qr.astype(np.float64) - c) ** 2).sum(1)[:, None]
+    assert np.max(np.abs(d2 - ref) / scale) < 2e-5
+    true = oracle.true_dist2(Qr, Xs)
+    enc = oracle_encode(plan, Xs, 4)
+    ref_o = oracle.estimate(Qr, M, c, plan.kept_widths, plan.kept_bits, enc.codes, enc.factors,
+                            enc.norm2)
+    e_gpu = oracle.relative_error(d2, true).mean()
+    e_orc = oracle.relative_error(ref_o, true).mean()
+    say(f"  mean relative error gpu {e_gpu:.4e} oracle {e_orc:.4e}")
+    assert abs(e_gpu - e_orc) <= 0.01 * e_orc
+
+
+def test_device_argument_errors(cfg1):
+    ds, X, plan = cfg1
+    x = to_dev(X[:10])
+    codes = torch.empty((10, plan.code_bytes), dtype=torch.uint8, device=cuda())
+    fac = torch.empty((10, plan.n_factors), dtype=torch.float32, device=cuda())
+    small = torch.empty(16, dtype=torch.uint8, device=cuda())
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode(plan, x, 4, codes, fac, workspace=small)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode(plan, x, -1, codes, fac)
+    L = saq.lib()
+    assert L.saq_encode(plan._h, x.data_ptr(), 0, 4, None, None, None, 0, None) == 0
+    assert L.saq_quantize(plan._h, x.data_ptr(), 128, 7, 10, None, 4, codes.data_ptr(),
+                          fac.data_ptr(), None) == 1          # unknown layout
+
+
+@pytest.mark.parametrize("bpd", [4.0, 2.0])
+def test_cfg2_full_size_sampled(bpd):
+    """1M x 960 cluster mixture at 2 and 4 b/dim, encoded in the single launch
+    pair the benchmark times; 3000 sampled records compared with the oracle."""
+    ds = synth.cfg2()
+    say(f"cfg2 full size bpd={bpd}: generating 1M x 960 on the device")
+    X = ds.rows_torch(ds.n, cuda())
+    sample = X[: 65536].cpu().numpy()
+    plan = saq.Plan.fit(sample, saq.PlanParams(bits_per_dim=bpd, fit_sample=0)).upload(0)
+    say(f"  plan widths={plan.widths} bits={plan.bits}")
+    codes, fac = saq.encode(plan, X, 4)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(5).choice(ds.n, 3000, replace=False))
+    it = torch.from_numpy(idx).to(cuda())
+    Xs = X[it].cpu().numpy()
+    packed, f = codes[it].cpu().numpy(), fac[it].cpu().numpy()
+    del X, codes, fac
+    compare(plan, packed, f, oracle_encode(plan, Xs, 4), label=f"cfg2 bpd={bpd}")
