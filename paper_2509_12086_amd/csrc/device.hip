@@ -66,47 +66,47 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int lk = (t & 1) * 16;        // k offset inside the tile
     const int64_t arow = m0 + lr;
     const bool arow_ok = arow < n;
-    const float* xrow = X + (arow_ok ? arow : 0) * int64_t(D);
+    // rows past n read row n-1 (always valid memory) and are zeroed on store
+    const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
     const float* brow = Mp + int64_t(n0 + lr) * k_pad;
     const bool do_norm = (norm2 != nullptr) && tile_n == 0;
     double nacc = 0.0;
 
-    float ra[16], rb[16];
-    auto load_tile = [&](int k0) {
+    // raw global values of the next tile; consumed only after the MFMAs of
+    // the current tile so the loads overlap the matrix work
+    float rx[16], rc[16], rb[16];
+    auto load_full = [&](int k0) {          // k0 + 32 <= D (and VEC)
         const int kb = k0 + lk;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
             const float4 c4 = *reinterpret_cast<const float4*>(cp + kb + 4 * q);
-            float4 x4;
-            if (VEC) {
-                if (arow_ok && kb + 4 * q + 4 <= D) {
-                    x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
-                } else {
-                    x4.x = (arow_ok && kb + 4 * q + 0 < D) ? xrow[kb + 4 * q + 0] : 0.f;
-                    x4.y = (arow_ok && kb + 4 * q + 1 < D) ? xrow[kb + 4 * q + 1] : 0.f;
-                    x4.z = (arow_ok && kb + 4 * q + 2 < D) ? xrow[kb + 4 * q + 2] : 0.f;
-                    x4.w = (arow_ok && kb + 4 * q + 3 < D) ? xrow[kb + 4 * q + 3] : 0.f;
-                }
-            } else {
-                x4.x = (arow_ok && kb + 4 * q + 0 < D) ? xrow[kb + 4 * q + 0] : 0.f;
-                x4.y = (arow_ok && kb + 4 * q + 1 < D) ? xrow[kb + 4 * q + 1] : 0.f;
-                x4.z = (arow_ok && kb + 4 * q + 2 < D) ? xrow[kb + 4 * q + 2] : 0.f;
-                x4.w = (arow_ok && kb + 4 * q + 3 < D) ? xrow[kb + 4 * q + 3] : 0.f;
-            }
-            if (do_norm) {
-                // exact (x - c)^2 in FP64; padding entries are 0 - 0
-                double d0 = double(x4.x) - double(c4.x), d1 = double(x4.y) - double(c4.y);
-                double d2 = double(x4.z) - double(c4.z), d3 = double(x4.w) - double(c4.w);
-                nacc = fma(d0, d0, nacc); nacc = fma(d1, d1, nacc);
-                nacc = fma(d2, d2, nacc); nacc = fma(d3, d3, nacc);
-            }
-            ra[4 * q + 0] = x4.x - c4.x; ra[4 * q + 1] = x4.y - c4.y;
-            ra[4 * q + 2] = x4.z - c4.z; ra[4 * q + 3] = x4.w - c4.w;
             const float4 b4 = *reinterpret_cast<const float4*>(brow + kb + 4 * q);
+            rx[4 * q + 0] = x4.x; rx[4 * q + 1] = x4.y; rx[4 * q + 2] = x4.z; rx[4 * q + 3] = x4.w;
+            rc[4 * q + 0] = c4.x; rc[4 * q + 1] = c4.y; rc[4 * q + 2] = c4.z; rc[4 * q + 3] = c4.w;
             rb[4 * q + 0] = b4.x; rb[4 * q + 1] = b4.y; rb[4 * q + 2] = b4.z; rb[4 * q + 3] = b4.w;
         }
     };
+    auto load_guarded = [&](int k0) {       // any tile: element loads below D
+        const int kb = k0 + lk;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            rx[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
+            rc[e] = cp[kb + e];
+            rb[e] = brow[kb + e];
+        }
+    };
     auto store_tile = [&](int buf) {
+        float ra[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            ra[e] = arow_ok ? rx[e] - rc[e] : 0.f;
+            if (do_norm) {
+                // exact (x - c)^2 in FP64; padding entries are 0 - 0
+                const double d = arow_ok ? double(rx[e]) - double(rc[e]) : 0.0;
+                nacc = fma(d, d, nacc);
+            }
+        }
         float* a = &As[buf][lr * LDS_STRIDE + lk];
         float* b = &Bs[buf][lr * LDS_STRIDE + lk];
 #pragma unroll
@@ -114,6 +114,11 @@ __global__ __launch_bounds__(256) void project_kernel(
             *reinterpret_cast<float4*>(a + 4 * q) = make_float4(ra[4 * q], ra[4 * q + 1], ra[4 * q + 2], ra[4 * q + 3]);
             *reinterpret_cast<float4*>(b + 4 * q) = make_float4(rb[4 * q], rb[4 * q + 1], rb[4 * q + 2], rb[4 * q + 3]);
         }
+    };
+    // full tiles use 16-byte loads when the rows allow it
+    const int kfull = VEC ? (D / TK) : 0;
+    auto load_tile = [&](int kt) {
+        if (kt < kfull) load_full(kt * TK); else load_guarded(kt * TK);
     };
 
     const int wave = t >> 6, lane = t & 63;
@@ -133,30 +138,32 @@ __global__ __launch_bounds__(256) void project_kernel(
     __syncthreads();
     for (int kt = 0; kt < ktiles; ++kt) {
         const int buf = kt & 1;
-        if (kt + 1 < ktiles) load_tile((kt + 1) * TK);
+        const bool more = kt + 1 < ktiles;
+        if (more) load_tile(kt + 1);
         const float* a0 = &As[buf][(wm * 64 + li) * LDS_STRIDE + lh * 16];
         const float* a1 = a0 + 32 * LDS_STRIDE;
         const float* b0 = &Bs[buf][(wn * 64 + li) * LDS_STRIDE + lh * 16];
         const float* b1 = b0 + 32 * LDS_STRIDE;
+        float A0[16], A1[16], B0[16], B1[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 va0 = *reinterpret_cast<const float4*>(a0 + 4 * q);
             const float4 va1 = *reinterpret_cast<const float4*>(a1 + 4 * q);
             const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
             const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
-            const float A0[4] = {va0.x, va0.y, va0.z, va0.w};
-            const float A1[4] = {va1.x, va1.y, va1.z, va1.w};
-            const float B0[4] = {vb0.x, vb0.y, vb0.z, vb0.w};
-            const float B1[4] = {vb1.x, vb1.y, vb1.z, vb1.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B0[j], acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B1[j], acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B0[j], acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B1[j], acc[1][1], 0, 0, 0);
-            }
+            A0[4 * q] = va0.x; A0[4 * q + 1] = va0.y; A0[4 * q + 2] = va0.z; A0[4 * q + 3] = va0.w;
+            A1[4 * q] = va1.x; A1[4 * q + 1] = va1.y; A1[4 * q + 2] = va1.z; A1[4 * q + 3] = va1.w;
+            B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
+            B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
         }
-        if (kt + 1 < ktiles) store_tile(buf ^ 1);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B0[j], acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B1[j], acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B0[j], acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B1[j], acc[1][1], 0, 0, 0);
+        }
+        if (more) store_tile(buf ^ 1);
         __syncthreads();
     }
 
@@ -207,18 +214,22 @@ __global__ __launch_bounds__(256) void project_kernel(
 // with u = code - (2^B-1)/2, ip = <u,o>, n = ||u||^2 and a move u_i += s,
 // L' > L  <=>  ip'^2 n > ip^2 n'  (given ip' > 0, which holds for every move
 // that passes this test because each term u_j o_j >= 0), i.e.
-//   s = +1:  n o (2 ip + o) > ip^2 (2u + 1)
-//   s = -1:  n o (o - 2 ip) > ip^2 (1 - 2u)
-// evaluated in FP64 (o is FP32, so these are within a few ulps of exact).
+//   s = +1:  n o (2 ip + o) > ip^2 (2u + 1)   <=>  A + Bv > 0
+//   s = -1:  n o (o - 2 ip) > ip^2 (1 - 2u)   <=>  A - Bv > 0
+// with A = n o^2 - ip^2 and Bv = 2 ip n o - 2u ip^2, evaluated in FP64 (o is
+// FP32, so both are within a few ulps of exact).  An all-zero segment has
+// o = 0 and ip = 0, so A = Bv = 0 and nothing is ever accepted.
 // +1 is tried first; after an accepted +1 the reverting -1 can never pass.
 // A round that accepts nothing leaves the state unchanged, so once no lane
 // of the wave accepted anything the remaining rounds are skipped.
 // ---------------------------------------------------------------------------
+constexpr int QCH = 8;   // dims per prefetch chunk in the quantize kernel
+
 template <typename CT, int LAYOUT>
 __global__ __launch_bounds__(64) void quantize_kernel(
     const float* __restrict__ O, int64_t ld, int64_t n, const SegEntry* __restrict__ segs,
     int n_kept, const float* __restrict__ norm2, int rounds, uint8_t* __restrict__ codes,
-    int64_t code_bytes, float* __restrict__ factors) {
+    int64_t code_bytes, int codes_align, float* __restrict__ factors) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     CT* lc = reinterpret_cast<CT*>(smem);
     const int lane = threadIdx.x;
@@ -237,14 +248,28 @@ __global__ __launch_bounds__(64) void quantize_kernel(
         const int W = e.width, B = e.bits;
         const int cmax = (1 << B) - 1;
         const float* os = ov + int64_t(e.col) * sd;
+        // chunk loader: QCH consecutive dims starting at i0, indices past the
+        // segment clamped to its last dim (loaded, never used)
+        auto load = [&](float* dst, int i0) {
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) dst[t] = os[int64_t(min(i0 + t, W - 1)) * sd];
+        };
+        float cur[QCH], nxt[QCH];
 
         // v_max = max |o_i| (exact in FP32) and ||o_s||^2 (FP64)
         float vmax = 0.f;
         double oo = 0.0;
-        for (int i = 0; i < W; ++i) {
-            const float o = os[i * sd];
-            vmax = fmaxf(vmax, fabsf(o));
-            oo = fma(double(o), double(o), oo);
+        load(cur, 0);
+        for (int i0 = 0; i0 < W; i0 += QCH) {
+            load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+#pragma unroll
+            for (int t = 0; t < QCH; ++t)
+                if (i0 + t < W) {
+                    vmax = fmaxf(vmax, fabsf(cur[t]));
+                    oo = fma(double(cur[t]), double(cur[t]), oo);
+                }
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
         }
         kept_norm += oo;
         const bool zero = !(vmax > 0.f);
@@ -257,47 +282,67 @@ __global__ __launch_bounds__(64) void quantize_kernel(
         const double inv = 1.0 / delta;
         const double half = 0.5 * double(cmax);
         double ip = 0.0, nn = 0.0;
-        for (int i = 0; i < W; ++i) {
-            const double o = double(os[i * sd]);
-            int c;
-            if (zero) {
-                c = (cmax + 1) >> 1;
-            } else {
-                const double a = o + vd;
-                double q = floor(a * inv);
-                if ((q + 1.0) * delta <= a) q += 1.0;
-                if (q * delta > a) q -= 1.0;
-                q = fmin(fmax(q, 0.0), double(cmax));
-                c = int(q);
+        for (int i0 = 0; i0 < W; i0 += QCH) {
+            load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) {
+                if (i0 + t >= W) continue;
+                const double o = double(cur[t]);
+                int c;
+                if (zero) {
+                    c = (cmax + 1) >> 1;
+                } else {
+                    const double a = o + vd;
+                    double q = floor(a * inv);
+                    if ((q + 1.0) * delta <= a) q += 1.0;
+                    if (q * delta > a) q -= 1.0;
+                    q = fmin(fmax(q, 0.0), double(cmax));
+                    c = int(q);
+                }
+                lc[(i0 + t) * 64 + lane] = CT(c);
+                const double u = double(c) - half;
+                ip = fma(u, o, ip);
+                nn = fma(u, u, nn);
             }
-            lc[i * 64 + lane] = CT(c);
-            const double u = double(c) - half;
-            ip = fma(u, o, ip);
-            nn = fma(u, u, nn);
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
         }
 
+        // code adjustment (Algorithm 1); cur holds chunk 0 again here
         if (B >= 2 && rounds > 0) {
             double P = 2.0 * ip, S = ip * ip;
             for (int rd = 0; rd < rounds; ++rd) {
                 int moved = 0;
-                for (int i = 0; i < W; ++i) {
-                    const double o = double(os[i * sd]);
-                    const int c = int(lc[i * 64 + lane]);
-                    const double w = double(2 * c - cmax);          // 2u
-                    const double no = nn * o;
-                    const double Lp = no * (P + o), Rp = fma(S, w, S);
-                    const double Lm = no * (o - P), Rm = fma(-S, w, S);
-                    const bool up = !zero && c < cmax && Lp > Rp;
-                    const bool dn = !zero && !up && c > 0 && Lm > Rm;
-                    if (up || dn) {
-                        const double sg = up ? 1.0 : -1.0;
-                        nn = nn + fma(sg, w, 1.0);      // (u + s)^2 = u^2 + 2su + 1
-                        ip = fma(sg, o, ip);
-                        P = 2.0 * ip;
-                        S = ip * ip;
-                        lc[i * 64 + lane] = CT(c + (up ? 1 : -1));
-                        moved = 1;
+                for (int i0 = 0; i0 < W; i0 += QCH) {
+                    load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+                    int cc[QCH];
+#pragma unroll
+                    for (int t = 0; t < QCH; ++t) cc[t] = int(lc[min(i0 + t, W - 1) * 64 + lane]);
+#pragma unroll
+                    for (int t = 0; t < QCH; ++t) {
+                        if (i0 + t >= W) continue;
+                        const double o = double(cur[t]);
+                        const int c = cc[t];
+                        const double w = double(2 * c - cmax);          // 2u
+                        // A = n o^2 - ip^2, Bv = 2 ip n o - ip^2 (2u):
+                        //   +1 passes iff A + Bv > 0, -1 iff A - Bv > 0
+                        const double no = nn * o;
+                        const double A = fma(no, o, -S);
+                        const double Bv = fma(no, P, -(S * w));
+                        const bool up = c < cmax && Bv > -A;
+                        const bool dn = !up && c > 0 && A > Bv;
+                        if (up || dn) {
+                            const double sg = up ? 1.0 : -1.0;
+                            nn = nn + fma(sg, w, 1.0);      // (u + s)^2 = u^2 + 2su + 1
+                            ip = fma(sg, o, ip);
+                            P = 2.0 * ip;
+                            S = ip * ip;
+                            lc[(i0 + t) * 64 + lane] = CT(c + (up ? 1 : -1));
+                            moved = 1;
+                        }
                     }
+#pragma unroll
+                    for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
                 }
                 if (!__any(moved)) break;
             }
@@ -306,20 +351,33 @@ __global__ __launch_bounds__(64) void quantize_kernel(
         // factor f_s = ||o_s||^2 / <u_s, o_s>
         if (live) factors[v * (n_kept + 1) + s] = zero ? 0.f : float(oo / ip);
 
-        // bit planes, most significant first; dim i -> byte i/8, bit i%8
+        // bit planes, most significant first; dim i -> byte i/8, bit i%8 of the
+        // plane.  Whole 32-bit words when every plane of the segment is
+        // 4-byte aligned, else 16-bit halves, else bytes.
         const int pb = (W + 7) >> 3;
-        for (int j = 0; j < pb; ++j) {
-            int cc[8];
+        const int al = pb | e.code_off | int(code_bytes) | codes_align;
+        const int unit = (al & 3) == 0 ? 4 : (al & 1) == 0 ? 2 : 1;
+        const int dims_per = unit * 8;
+        for (int j0 = 0; j0 < W; j0 += dims_per) {
+            uint32_t word[16];
 #pragma unroll
-            for (int t2 = 0; t2 < 8; ++t2) {
-                const int i = 8 * j + t2;
-                cc[t2] = i < W ? int(lc[i * 64 + lane]) : 0;
+            for (int p = 0; p < 16; ++p) word[p] = 0u;
+            for (int t = 0; t < dims_per && j0 + t < W; ++t) {
+                const uint32_t c = uint32_t(lc[(j0 + t) * 64 + lane]);
+#pragma unroll
+                for (int p = 0; p < 16; ++p)
+                    if (p < B) word[p] |= ((c >> p) & 1u) << t;
             }
-            for (int p = B - 1; p >= 0; --p) {
-                unsigned byte = 0;
+            if (live) {
+                const int64_t byte0 = e.code_off + (j0 >> 3);
 #pragma unroll
-                for (int t2 = 0; t2 < 8; ++t2) byte |= unsigned((cc[t2] >> p) & 1) << t2;
-                if (live) rec[e.code_off + int64_t(B - 1 - p) * pb + j] = uint8_t(byte);
+                for (int p = 0; p < 16; ++p) {
+                    if (p >= B) continue;
+                    uint8_t* dst = rec + byte0 + int64_t(B - 1 - p) * pb;
+                    if (unit == 4) *reinterpret_cast<uint32_t*>(dst) = word[p];
+                    else if (unit == 2) *reinterpret_cast<uint16_t*>(dst) = uint16_t(word[p]);
+                    else *dst = uint8_t(word[p]);
+                }
             }
         }
     }
@@ -447,9 +505,12 @@ saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int la
         return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the quantize kernel's "
                                            "LDS code buffer (1024 dims at <= 8 bits, 512 above)");
     const dim3 grid(unsigned((n + 63) / 64));
+    // 4 when the codes base is 4-byte aligned, 2 when 2-byte aligned, else 1
+    const uintptr_t cb = reinterpret_cast<uintptr_t>(codes);
+    const int codes_align = (cb & 3) == 0 ? 4 : (cb & 1) == 0 ? 2 : 1;
 #define SAQ_LAUNCH_Q(CT, L)                                                                       \
     hipLaunchKernelGGL((quantize_kernel<CT, L>), grid, dim3(64), lds, st, O, ld, n, dev_seg(p),   \
-                       p->n_kept, norm2, rounds, codes, p->code_bytes, factors)
+                       p->n_kept, norm2, rounds, codes, p->code_bytes, codes_align, factors)
     if (layout == LAYOUT_DIMS) {
         if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_DIMS); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_DIMS);
     } else {
