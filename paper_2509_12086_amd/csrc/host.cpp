@@ -61,19 +61,24 @@ void build_staging(saq_plan& p) {
 
 struct Rot { int32_t i; double c, s; };
 
-static void apply_rotations(std::vector<double>& Z, int n, const std::vector<Rot>& rots) {
+// Apply recorded Givens rotations (in order) to the rows i, i+1 of Zt (the
+// transposed basis, n x n row-major), in parallel over column blocks so that
+// each rotation is a contiguous two-row update.
+static void apply_rotations(std::vector<double>& Zt, int n, const std::vector<Rot>& rots) {
     if (rots.empty()) return;
     const int64_t nrot = int64_t(rots.size());
+    const int CB = 128;
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int r0 = 0; r0 < n; r0 += 8) {
-        const int r1 = std::min(n, r0 + 8);
+    for (int k0 = 0; k0 < n; k0 += CB) {
+        const int k1 = std::min(n, k0 + CB);
         for (int64_t t = 0; t < nrot; ++t) {
             const Rot& R = rots[size_t(t)];
-            for (int k = r0; k < r1; ++k) {
-                double* z = &Z[size_t(k) * n];
-                const double f = z[R.i + 1];
-                z[R.i + 1] = R.s * z[R.i] + R.c * f;
-                z[R.i] = R.c * z[R.i] - R.s * f;
+            double* zi = &Zt[size_t(R.i) * n];
+            double* zj = zi + n;
+            for (int k = k0; k < k1; ++k) {
+                const double f = zj[k];
+                zj[k] = R.s * zi[k] + R.c * f;
+                zi[k] = R.c * zi[k] - R.s * f;
             }
         }
     }
@@ -124,23 +129,44 @@ static bool sym_eigen(std::vector<double>& A, int n, std::vector<double>& w, std
     }
     if (n >= 2) e[1] = A[size_t(1) * n + 0];
     for (int i = 0; i < n; ++i) d[i] = A[size_t(i) * n + i];
-    // basis Z = H_{n-1} ... H_2 (each reflector acts on rows 0..k-1 from the left)
+    // basis Z = H_{n-1} ... H_2 applied to I (H_k acts on rows 0..k-1 from
+    // the left).  Applied in ascending k, the rows 0..k-1 are still zero
+    // outside columns 0..k-1, so each step updates a k x k block; it is done
+    // as row-contiguous sweeps in parallel over column blocks.
     V.assign(size_t(n) * n, 0.0);
     for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
     for (int k = 2; k < n; ++k) {
         if (hs[size_t(k)] == 0.0) continue;
         const std::vector<double>& v = hv[size_t(k)];
         const double beta = hs[size_t(k)];
+        const int JB = 64;
 #pragma omp parallel for schedule(static)
-        for (int j = 0; j < n; ++j) {
-            double s = 0.0;
-            for (int i = 0; i < k; ++i) s += v[i] * V[size_t(i) * n + j];
-            s *= beta;
-            if (s != 0.0)
-                for (int i = 0; i < k; ++i) V[size_t(i) * n + j] -= s * v[i];
+        for (int j0 = 0; j0 < k; j0 += JB) {
+            const int j1 = std::min(k, j0 + JB);
+            double w[64];
+            for (int j = j0; j < j1; ++j) w[j - j0] = 0.0;
+            for (int i = 0; i < k; ++i) {
+                const double vi = v[i];
+                const double* row = &V[size_t(i) * n];
+                for (int j = j0; j < j1; ++j) w[j - j0] += vi * row[j];
+            }
+            for (int j = j0; j < j1; ++j) w[j - j0] *= beta;
+            for (int i = 0; i < k; ++i) {
+                const double vi = v[i];
+                double* row = &V[size_t(i) * n];
+                for (int j = j0; j < j1; ++j) row[j] -= vi * w[j - j0];
+            }
         }
     }
     hv.clear();
+    // the QL rotations act on columns of V: work on its transpose
+    {
+        std::vector<double> T(size_t(n) * n);
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) T[size_t(j) * n + i] = V[size_t(i) * n + j];
+        V.swap(T);
+    }
     // QL with implicit shifts on (d, e); e[i] couples i and i+1 after the shift
     for (int i = 1; i < n; ++i) e[i - 1] = e[i];
     if (n > 0) e[n - 1] = 0.0;
@@ -185,16 +211,16 @@ static bool sym_eigen(std::vector<double>& A, int n, std::vector<double>& w, std
         } while (m != l);
     }
     apply_rotations(V, n, rots);
-    // sort descending
+    // sort descending; V now holds eigenvector j in its row j
     std::vector<int> ord(n);
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] > d[b]; });
     w.resize(n);
     std::vector<double> V2(size_t(n) * n);
-    for (int j = 0; j < n; ++j) {
-        w[j] = d[ord[j]];
-        for (int i = 0; i < n; ++i) V2[size_t(i) * n + j] = V[size_t(i) * n + ord[j]];
-    }
+    for (int j = 0; j < n; ++j) w[j] = d[ord[j]];
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V2[size_t(i) * n + j] = V[size_t(ord[j]) * n + i];
     V.swap(V2);
     return true;
 }
