@@ -63,6 +63,9 @@ typedef struct {
     int32_t  rotate_segments; /* 1: random orthonormal rotation inside each kept segment (Section 4.1) */
     int64_t  fit_sample;      /* rows used for mean/covariance (0 = all); an evenly spaced subset */
     uint64_t seed;            /* seeds the per-segment rotations */
+    int32_t  projection_accumulation; /* 0 auto: FP64 k-tile totals when D > 1024 or a kept
+                                         segment has >= 8 bits, else FP32; 1: FP32 throughout;
+                                         2: FP32 per 32-wide k-tile, FP64 across tiles */
 } saq_plan_params;
 
 typedef struct {
@@ -78,10 +81,11 @@ typedef struct {
     double  min_error;    /* minimum of the model over all plans within the quota */
     int64_t quota_bits;   /* Q_quota */
     int64_t used_bits;    /* sum B * |Seg| */
+    int32_t projection_fp64_totals; /* 1 when the projection adds its k-tiles in FP64 */
 } saq_plan_info;
 
 /* Defaults: B=4, g=16, max_bits=9, max_width=512, seg_eps=1e-3, rotation on,
-   fit_sample=65536, seed=1. */
+   fit_sample=65536, seed=1, projection_accumulation=0 (auto). */
 void saq_default_params(saq_plan_params* p);
 
 /* Fit a plan on host rows X [n x D] (row-major FP32): mean c, covariance and
@@ -167,6 +171,36 @@ int64_t    saq_estimate_workspace_bytes(const saq_plan* plan, int32_t nq);
 saq_status saq_estimate_dist(const saq_plan* plan, const float* Q_dev, int32_t nq,
                              const uint8_t* codes_dev, const float* factors_dev, int64_t n,
                              float* dist2_dev, void* ws_dev, int64_t ws_bytes, void* stream);
+
+/* Batched encode: many datasets, each with its own uploaded plan (uneven
+   segment widths and bits), in two grouped launches for the whole batch --
+   one for every dataset's projection tiles, one for every dataset's
+   quantize/adjust/pack blocks -- however many datasets there are.  Every
+   dataset gets exactly the records saq_encode would give it.  ws_dev:
+   saq_encode_batched_workspace_bytes() bytes (the projected rows of all
+   datasets). */
+#define SAQ_BATCH_MAX 16
+typedef struct {
+    const saq_plan* plan;      /* uploaded plan of this dataset */
+    const float* X_dev;        /* [n x D] FP32 rows */
+    int64_t n;                 /* rows (0 = nothing to do for this entry) */
+    uint8_t* codes_dev;        /* [n x code_bytes] */
+    float* factors_dev;        /* [n x n_factors] */
+} saq_batch_item;
+
+/* Launch shape (picked by the autotuner; zero fields take defaults). */
+typedef struct {
+    int32_t quant_waves;     /* waves (of 64 vectors) per quantize workgroup: 1, 2 or 4 (0: 1);
+                                halved while their LDS code buffers exceed 64 KiB */
+    int32_t gemm_xcd_order;  /* 1: XCD-aware projection tile order (default), 0: row-major */
+    int32_t reserved;        /* must be 0 */
+} saq_batch_tuning;
+
+int64_t    saq_encode_batched_workspace_bytes(const saq_batch_item* items, int32_t count,
+                                              const saq_batch_tuning* tuning);
+saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_t rounds,
+                              const saq_batch_tuning* tuning, void* ws_dev, int64_t ws_bytes,
+                              void* stream);
 
 const char* saq_last_error(void);
 const char* saq_version(void);

@@ -36,7 +36,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("bits_per_dim", ctypes.c_double), ("granularity", ctypes.c_int32),
                 ("max_bits", ctypes.c_int32), ("max_width", ctypes.c_int32),
                 ("seg_eps", ctypes.c_double), ("rotate_segments", ctypes.c_int32),
-                ("fit_sample", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+                ("fit_sample", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("projection_accumulation", ctypes.c_int32)]
 
 
 class _Info(ctypes.Structure):
@@ -45,7 +46,7 @@ class _Info(ctypes.Structure):
                 ("n_factors", ctypes.c_int32), ("max_kept_width", ctypes.c_int32),
                 ("max_kept_bits", ctypes.c_int32), ("model_error", ctypes.c_double),
                 ("min_error", ctypes.c_double), ("quota_bits", ctypes.c_int64),
-                ("used_bits", ctypes.c_int64)]
+                ("used_bits", ctypes.c_int64), ("projection_fp64_totals", ctypes.c_int32)]
 
 
 _lib = None
@@ -53,7 +54,20 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_plan_info_get", "saq_plan_segments", "saq_plan_arrays", "saq_plan_save",
            "saq_plan_load", "saq_plan_free", "saq_plan_device_bytes", "saq_plan_upload",
            "saq_encode_workspace_bytes", "saq_encode", "saq_project", "saq_quantize",
-           "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_last_error", "saq_version")
+           "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_encode_batched_workspace_bytes",
+           "saq_encode_batched", "saq_last_error", "saq_version")
+
+BATCH_MAX = 16
+
+
+class _BatchItem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("X_dev", ctypes.c_void_p), ("n", ctypes.c_int64),
+                ("codes_dev", ctypes.c_void_p), ("factors_dev", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("quant_waves", ctypes.c_int32), ("gemm_xcd_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 def lib() -> ctypes.CDLL:
@@ -86,6 +100,8 @@ def lib() -> ctypes.CDLL:
         "saq_quantize": (i32, [P, P, i64, i32, i64, P, i32, P, P, P]),
         "saq_estimate_workspace_bytes": (i64, [P, i32]),
         "saq_estimate_dist": (i32, [P, P, i32, P, P, i64, P, P, i64, P]),
+        "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
+        "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
         "saq_last_error": (ctypes.c_char_p, []),
         "saq_version": (ctypes.c_char_p, []),
     }
@@ -117,11 +133,12 @@ class PlanParams:
     rotate_segments: bool = True
     fit_sample: int = 65536
     seed: int = 1
+    projection_accumulation: int = 0     # 0 auto, 1 FP32, 2 FP64 k-tile totals
 
     def _c(self) -> _Params:
         return _Params(float(self.bits_per_dim), int(self.granularity), int(self.max_bits),
                        int(self.max_width), float(self.seg_eps), int(bool(self.rotate_segments)),
-                       int(self.fit_sample), int(self.seed))
+                       int(self.fit_sample), int(self.seed), int(self.projection_accumulation))
 
 
 def _torch():
@@ -363,3 +380,56 @@ def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:
             pos += pb
         off += w
     return out
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchTuning:
+    """Launch shape of the batched launches (saq_batch_tuning)."""
+    quant_waves: int = 1
+    gemm_xcd_order: bool = True
+
+    def _c(self) -> _Tuning:
+        return _Tuning(int(self.quant_waves), int(bool(self.gemm_xcd_order)), 0)
+
+
+def _batch_struct(entries):
+    arr = (_BatchItem * len(entries))()
+    for i, (plan, X, codes, fac) in enumerate(entries):
+        arr[i] = _BatchItem(plan._h.value, _dev_ptr(X), X.shape[0], _dev_ptr(codes), _dev_ptr(fac))
+    return arr
+
+
+def batched_workspace_bytes(entries, tuning: Optional[BatchTuning] = None) -> int:
+    arr = _batch_struct([(p, X, None, None) for p, X, *_ in entries])
+    t = (tuning or BatchTuning())._c()
+    need = int(lib().saq_encode_batched_workspace_bytes(arr, len(entries), ctypes.byref(t)))
+    if need < 0:
+        raise SaqError(1, lib().saq_last_error().decode())
+    return need
+
+
+def encode_batched(entries, rounds: int = 4, tuning: Optional[BatchTuning] = None,
+                   workspace=None, stream=None):
+    """saq_encode_batched over ``entries`` = [(plan, X), ...] or
+    [(plan, X, codes, factors), ...]; returns [(codes, factors), ...]."""
+    torch = _torch()
+    if not 1 <= len(entries) <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1..{BATCH_MAX} datasets")
+    full = []
+    for e in entries:
+        plan, X = e[0], e[1]
+        _require_cuda_f32(X, "X", plan.D)
+        codes, fac = _alloc_out(plan, X.shape[0], X.device, *(e[2:4] if len(e) > 2 else ()))
+        full.append((plan, X, codes, fac))
+    arr = _batch_struct(full)
+    t = (tuning or BatchTuning())._c()
+    dev = full[0][1].device
+    if workspace is None:
+        need = int(lib().saq_encode_batched_workspace_bytes(arr, len(full), ctypes.byref(t)))
+        if need < 0:
+            raise SaqError(1, lib().saq_last_error().decode())
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().saq_encode_batched(arr, len(full), rounds, ctypes.byref(t), _dev_ptr(workspace),
+                                    workspace.numel() * workspace.element_size(),
+                                    _stream_ptr(stream, dev)))
+    return [(c, f) for _, _, c, f in full]

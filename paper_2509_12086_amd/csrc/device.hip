@@ -45,19 +45,17 @@ enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1 };
 // tiles x, x+8, ... and, inside each, all column tiles back to back, so the
 // X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
 // ---------------------------------------------------------------------------
-template <bool VEC, int LAYOUT>
-__global__ __launch_bounds__(256) void project_kernel(
-    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
-    const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) float As[2][TM * LDS_STRIDE];
-    __shared__ __attribute__((aligned(16))) float Bs[2][TN * LDS_STRIDE];
+constexpr int GEMM_LDS_FLOATS = 2 * (TM + TN) * LDS_STRIDE;   // 73,728 bytes
 
-    const int bid = blockIdx.x;
-    const int xcd = bid % NXCD, local = bid / NXCD;
-    const int tile_n = local % tiles_n;
-    const int tile_m = (local / tiles_n) * NXCD + xcd;
-    if (tile_m >= tiles_m) return;
+// One 128 x 128 output tile (tile_m, tile_n).  lds: GEMM_LDS_FLOATS floats,
+// free on entry and on return (the last k-step ends with a barrier).
+template <int LAYOUT, bool ACC64>
+__device__ __forceinline__ void gemm_tile(
+    bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
+    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
+    float (*As)[TM * LDS_STRIDE] = reinterpret_cast<float (*)[TM * LDS_STRIDE]>(lds);
+    float (*Bs)[TN * LDS_STRIDE] = reinterpret_cast<float (*)[TN * LDS_STRIDE]>(lds + 2 * TM * LDS_STRIDE);
     const int64_t m0 = int64_t(tile_m) * TM;
     const int n0 = tile_n * TN;
 
@@ -116,7 +114,7 @@ __global__ __launch_bounds__(256) void project_kernel(
         }
     };
     // full tiles use 16-byte loads when the rows allow it
-    const int kfull = VEC ? (D / TK) : 0;
+    const int kfull = vec ? (D / TK) : 0;
     auto load_tile = [&](int kt) {
         if (kt < kfull) load_full(kt * TK); else load_guarded(kt * TK);
     };
@@ -124,13 +122,21 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int wave = t >> 6, lane = t & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 31, lh = lane >> 5;
+    // ACC64: each 32-wide k-tile is accumulated by the MFMAs in FP32 from
+    // zero and then added into FP64 totals, so the FP32 rounding error grows
+    // with the tile length (32) rather than with D.  Otherwise the MFMAs
+    // accumulate the whole dot product in FP32.
     floatx16 acc[2][2];
+    double tot[2][2][ACC64 ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+#pragma unroll
+            for (int r = 0; r < (ACC64 ? 16 : 1); ++r) tot[i][j][r] = 0.0;
+        }
 
     const int ktiles = k_pad / TK;
     load_tile(0);
@@ -163,6 +169,17 @@ __global__ __launch_bounds__(256) void project_kernel(
             acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B0[j], acc[1][0], 0, 0, 0);
             acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B1[j], acc[1][1], 0, 0, 0);
         }
+        if (ACC64) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        tot[i][j][r & (ACC64 ? 15 : 0)] += double(acc[i][j][r]);
+                        acc[i][j][r] = 0.f;
+                    }
+        }
         if (more) store_tile(buf ^ 1);
         __syncthreads();
     }
@@ -183,8 +200,16 @@ __global__ __launch_bounds__(256) void project_kernel(
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int64_t row = m0 + wm * 64 + bi * 32 + 8 * g + 4 * lh;
-                const float v0 = acc[bi][bj][4 * g + 0], v1 = acc[bi][bj][4 * g + 1];
-                const float v2 = acc[bi][bj][4 * g + 2], v3 = acc[bi][bj][4 * g + 3];
+                float v0, v1, v2, v3;
+                if (ACC64) {
+                    v0 = float(tot[bi][bj][(4 * g + 0) & (ACC64 ? 15 : 0)]);
+                    v1 = float(tot[bi][bj][(4 * g + 1) & (ACC64 ? 15 : 0)]);
+                    v2 = float(tot[bi][bj][(4 * g + 2) & (ACC64 ? 15 : 0)]);
+                    v3 = float(tot[bi][bj][(4 * g + 3) & (ACC64 ? 15 : 0)]);
+                } else {
+                    v0 = acc[bi][bj][4 * g + 0]; v1 = acc[bi][bj][4 * g + 1];
+                    v2 = acc[bi][bj][4 * g + 2]; v3 = acc[bi][bj][4 * g + 3];
+                }
                 if (LAYOUT == LAYOUT_DIMS) {
                     float* dst = O + int64_t(col) * ld + row;
                     if (row + 3 < n) {
@@ -203,6 +228,20 @@ __global__ __launch_bounds__(256) void project_kernel(
                 }
             }
         }
+}
+
+template <bool VEC, int LAYOUT, bool ACC64>
+__global__ __launch_bounds__(256) void project_kernel(
+    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
+    const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(16))) float lds[GEMM_LDS_FLOATS];
+    const int bid = blockIdx.x;
+    const int xcd = bid % NXCD, local = bid / NXCD;
+    const int tile_n = local % tiles_n;
+    const int tile_m = (local / tiles_n) * NXCD + xcd;
+    if (tile_m >= tiles_m) return;
+    gemm_tile<LAYOUT, ACC64>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,15 +264,15 @@ __global__ __launch_bounds__(256) void project_kernel(
 // ---------------------------------------------------------------------------
 constexpr int QCH = 8;   // dims per prefetch chunk in the quantize kernel
 
+// One wave quantizes vectors v0 .. v0+63 (one per lane).  lc: this wave's
+// code buffer, [max kept width][64] entries (LDS or global memory).
 template <typename CT, int LAYOUT>
-__global__ __launch_bounds__(64) void quantize_kernel(
-    const float* __restrict__ O, int64_t ld, int64_t n, const SegEntry* __restrict__ segs,
-    int n_kept, const float* __restrict__ norm2, int rounds, uint8_t* __restrict__ codes,
-    int64_t code_bytes, int codes_align, float* __restrict__ factors) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    CT* lc = reinterpret_cast<CT*>(smem);
-    const int lane = threadIdx.x;
-    const int64_t v = int64_t(blockIdx.x) * 64 + lane;
+__device__ __forceinline__ void quantize_wave(
+    const float* __restrict__ O, int64_t ld, int64_t n, int64_t v0, int lane,
+    const SegEntry* __restrict__ segs, int n_kept, const float* __restrict__ norm2, int rounds,
+    uint8_t* __restrict__ codes, int64_t code_bytes, int codes_align,
+    float* __restrict__ factors, CT* __restrict__ lc) {
+    const int64_t v = v0 + lane;
     const bool live = v < n;
     const int64_t vv = live ? v : n - 1;
     // element (vector vv, kept dim j)
@@ -384,6 +423,87 @@ __global__ __launch_bounds__(64) void quantize_kernel(
     if (live) factors[v * (n_kept + 1) + n_kept] = norm2 ? norm2[v] : float(kept_norm);
 }
 
+template <typename CT, int LAYOUT>
+__global__ __launch_bounds__(64) void quantize_kernel(
+    const float* __restrict__ O, int64_t ld, int64_t n, const SegEntry* __restrict__ segs,
+    int n_kept, const float* __restrict__ norm2, int rounds, uint8_t* __restrict__ codes,
+    int64_t code_bytes, int codes_align, float* __restrict__ factors) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    quantize_wave<CT, LAYOUT>(O, ld, n, int64_t(blockIdx.x) * 64, threadIdx.x, segs, n_kept,
+                              norm2, rounds, codes, code_bytes, codes_align, factors,
+                              reinterpret_cast<CT*>(smem));
+}
+
+// ---------------------------------------------------------------------------
+// Batched encode: up to BATCH_MAX datasets, each with its own plan (uneven
+// segment widths and bits), in two grouped launches for the whole batch:
+// one runs every dataset's projection tiles, the next every dataset's
+// quantize/adjust/pack blocks.  A workgroup finds its dataset from the block
+// ranges in the launch arguments; no workgroup ever waits for another.
+// ---------------------------------------------------------------------------
+constexpr int BATCH_MAX = 16;
+
+struct GemmSet {
+    const float* X; int64_t n; int D; int vec; int acc64;
+    const float* Mp; int k_pad; const float* cp; int dk; int tiles_m; int tiles_n;
+    float* O; int64_t ld; float* norm2;
+    int64_t first_block;
+};
+struct GemmArgs { GemmSet set[BATCH_MAX]; int count; int xcd_order; };
+
+template <bool ACC64>
+__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) {
+    __shared__ __attribute__((aligned(16))) float lds[GEMM_LDS_FLOATS];
+    const int64_t b = blockIdx.x;
+    int d = 0;
+    while (d + 1 < args.count && b >= args.set[d + 1].first_block) ++d;
+    const GemmSet& S = args.set[d];
+    const int64_t lb = b - S.first_block;
+    int tile_m, tile_n;
+    if (args.xcd_order) {
+        // every dataset's block range starts at a multiple of 8, so lb % 8 is
+        // the XCD this workgroup runs on
+        const int xcd = int(lb % NXCD);
+        const int64_t local = lb / NXCD;
+        tile_n = int(local % S.tiles_n);
+        tile_m = int(local / S.tiles_n) * NXCD + xcd;
+    } else {
+        tile_m = int(lb / S.tiles_n);
+        tile_n = int(lb % S.tiles_n);
+    }
+    if (tile_m >= S.tiles_m) return;
+    if (S.acc64)
+        gemm_tile<LAYOUT_DIMS, ACC64>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
+                                      S.ld, S.norm2, tile_m, tile_n, lds);
+    else
+        gemm_tile<LAYOUT_DIMS, false>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
+                                      S.ld, S.norm2, tile_m, tile_n, lds);
+}
+
+struct QuantSet {
+    const float* O; int64_t ld; int64_t n;
+    const SegEntry* segs; int n_kept; const float* norm2;
+    uint8_t* codes; int64_t code_bytes; int codes_align; float* factors;
+    int64_t first_block;
+};
+struct QuantArgs { QuantSet set[BATCH_MAX]; int count; int rounds; int wmax; };
+
+template <typename CT>
+__global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs args) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int64_t b = blockIdx.x;
+    int d = 0;
+    while (d + 1 < args.count && b >= args.set[d + 1].first_block) ++d;
+    const QuantSet& S = args.set[d];
+    const int waves = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t v0 = (b - S.first_block) * 64 * waves + int64_t(wave) * 64;
+    if (v0 >= S.n) return;
+    CT* lc = reinterpret_cast<CT*>(smem) + int64_t(wave) * args.wmax * 64;
+    quantize_wave<CT, LAYOUT_DIMS>(S.O, S.ld, S.n, v0, lane, S.segs, S.n_kept, S.norm2,
+                                   args.rounds, S.codes, S.code_bytes, S.codes_align,
+                                   S.factors, lc);
+}
+
 // ---------------------------------------------------------------------------
 // Estimate scan: one thread per stored record, QG queries per block.  For
 // each kept segment the projected queries' slice is staged in LDS; the
@@ -481,14 +601,17 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
     const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     if (layout == LAYOUT_DIMS && ((reinterpret_cast<uintptr_t>(O) & 15) != 0 || (ld % 4) != 0))
         return saq::fail(SAQ_EINVAL, "dims-major output needs a 16-byte aligned buffer and ld % 4 == 0");
-#define SAQ_LAUNCH_PROJ(V, L)                                                                     \
-    hipLaunchKernelGGL((project_kernel<V, L>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),      \
+#define SAQ_LAUNCH_PROJ(V, L, A)                                                                  \
+    hipLaunchKernelGGL((project_kernel<V, L, A>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),   \
                        p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n)
+#define SAQ_LAUNCH_PROJ2(V, L) \
+    do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true); else SAQ_LAUNCH_PROJ(V, L, false); } while (0)
     if (layout == LAYOUT_DIMS) {
-        if (vec) SAQ_LAUNCH_PROJ(true, LAYOUT_DIMS); else SAQ_LAUNCH_PROJ(false, LAYOUT_DIMS);
+        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_DIMS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_DIMS);
     } else {
-        if (vec) SAQ_LAUNCH_PROJ(true, LAYOUT_ROWS); else SAQ_LAUNCH_PROJ(false, LAYOUT_ROWS);
+        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_ROWS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_ROWS);
     }
+#undef SAQ_LAUNCH_PROJ2
 #undef SAQ_LAUNCH_PROJ
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "project_kernel launch");
@@ -524,6 +647,83 @@ saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int la
 // workspace of saq_encode: O (dims-major, [D_kept x ld]) then norm2 [n]
 int64_t enc_ld(int64_t n) { return round_up(std::max<int64_t>(n, 1), 4); }
 
+
+struct BatchPlan {
+    GemmArgs g{};
+    QuantArgs q{};
+    int64_t gemm_blocks = 0, quant_blocks = 0, ws_need = 0;
+    int waves = 1;
+    bool wide = false;
+    size_t lds = 0;
+};
+
+// Lays out the workspace (per dataset: projected rows in the dims layout and
+// ||x - c||^2) and fills both launches' arguments.  With ws == nullptr only
+// the size is meaningful.
+saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds,
+                      const saq_batch_tuning* tuning, void* ws, BatchPlan& B,
+                      bool check_buffers = true) {
+    if (!items || count <= 0 || count > BATCH_MAX)
+        return saq::fail(SAQ_EINVAL, "batch must hold 1..16 datasets");
+    if (rounds < 0) return saq::fail(SAQ_EINVAL, "rounds < 0");
+    int wmax = 1;
+    for (int i = 0; i < count; ++i) {
+        const saq_batch_item& it = items[i];
+        if (!uploaded(it.plan)) return saq::fail(SAQ_EINVAL, "batch plan not uploaded");
+        if (it.n < 0) return saq::fail(SAQ_EINVAL, "negative n");
+        if (check_buffers && it.n > 0 && (!it.X_dev || !it.codes_dev || !it.factors_dev))
+            return saq::fail(SAQ_EINVAL, "null buffer");
+        if (it.n > 0) {
+            wmax = std::max(wmax, it.plan->max_kept_w);
+            B.wide |= it.plan->max_kept_b > 8;
+        }
+    }
+    const size_t cs = B.wide ? 2 : 1;
+    const int want = tuning && tuning->quant_waves > 0 ? tuning->quant_waves : 1;
+    if (want != 1 && want != 2 && want != 4) return saq::fail(SAQ_EINVAL, "quant_waves must be 1, 2 or 4");
+    if (size_t(wmax) * 64 * cs > kMaxDynLds)
+        return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the quantize kernel's "
+                                           "LDS code buffer (1024 dims at <= 8 bits, 512 above)");
+    B.waves = want;
+    while (B.waves > 1 && size_t(B.waves) * wmax * 64 * cs > kMaxDynLds) B.waves >>= 1;
+    B.lds = size_t(B.waves) * wmax * 64 * cs;
+    const int xcd = !tuning || tuning->gemm_xcd_order != 0;
+
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) { const int64_t o = off; off += (bytes + 255) & ~int64_t(255); return o; };
+    B.g.count = B.q.count = 0;
+    B.g.xcd_order = xcd;
+    B.q.rounds = rounds;
+    B.q.wmax = wmax;
+    for (int i = 0; i < count; ++i) {
+        const saq_batch_item& it = items[i];
+        if (it.n == 0) continue;
+        const saq_plan* p = it.plan;
+        const int64_t ld = enc_ld(it.n);
+        float* O = reinterpret_cast<float*>(base + take(int64_t(p->D_kept) * ld * 4));
+        float* nrm = reinterpret_cast<float*>(base + take(it.n * 4));
+        GemmSet& G = B.g.set[B.g.count++];
+        G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
+        G.vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
+        G.Mp = dev_M(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
+        G.tiles_m = int((it.n + TM - 1) / TM); G.tiles_n = p->layout.n_pad / TN;
+        G.O = O; G.ld = ld; G.norm2 = nrm;
+        G.first_block = B.gemm_blocks;
+        B.gemm_blocks += xcd ? int64_t(NXCD) * ((G.tiles_m + NXCD - 1) / NXCD) * G.tiles_n
+                             : int64_t(G.tiles_m) * G.tiles_n;
+        QuantSet& Q = B.q.set[B.q.count++];
+        Q.O = O; Q.ld = ld; Q.n = it.n; Q.segs = dev_seg(p); Q.n_kept = p->n_kept; Q.norm2 = nrm;
+        Q.codes = it.codes_dev; Q.code_bytes = p->code_bytes;
+        const uintptr_t cb = reinterpret_cast<uintptr_t>(it.codes_dev);
+        Q.codes_align = (cb & 3) == 0 ? 4 : (cb & 1) == 0 ? 2 : 1;
+        Q.factors = it.factors_dev;
+        Q.first_block = B.quant_blocks;
+        B.quant_blocks += (it.n + 64 * B.waves - 1) / (64 * B.waves);
+    }
+    B.ws_need = off + 256;
+    return SAQ_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -599,6 +799,41 @@ saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t roun
     saq_status s = launch_project(p, X, n, O, ld, LAYOUT_DIMS, nrm, st);
     if (s != SAQ_OK) return s;
     return launch_quantize(p, O, ld, LAYOUT_DIMS, n, nrm, rounds, codes, factors, st);
+}
+
+int64_t saq_encode_batched_workspace_bytes(const saq_batch_item* items, int32_t count,
+                                           const saq_batch_tuning* tuning) {
+    BatchPlan B;
+    if (plan_batch(items, count, 0, tuning, nullptr, B, false) != SAQ_OK) return -1;
+    return B.ws_need;
+}
+
+saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_t rounds,
+                              const saq_batch_tuning* tuning, void* ws, int64_t ws_bytes,
+                              void* stream) {
+    if (!ws) return saq::fail(SAQ_EINVAL, "null workspace");
+    BatchPlan B;
+    if (saq_status s = plan_batch(items, count, rounds, tuning, ws, B); s != SAQ_OK) return s;
+    if (ws_bytes < B.ws_need) return saq::fail(SAQ_EINVAL, "workspace too small");
+    if (B.g.count == 0) return SAQ_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    bool any64 = false;
+    for (int i = 0; i < B.g.count; ++i) any64 |= B.g.set[i].acc64 != 0;
+    // one instantiation handles both kinds of datasets; the FP32-only one
+    // keeps the register budget of two workgroups per compute unit
+    if (any64)
+        hipLaunchKernelGGL(grouped_gemm_kernel<true>, dim3(unsigned(B.gemm_blocks)), dim3(256), 0, st, B.g);
+    else
+        hipLaunchKernelGGL(grouped_gemm_kernel<false>, dim3(unsigned(B.gemm_blocks)), dim3(256), 0, st, B.g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "grouped_gemm_kernel launch");
+    const dim3 qb(unsigned(64 * B.waves));
+    if (B.wide)
+        hipLaunchKernelGGL(grouped_quantize_kernel<uint16_t>, dim3(unsigned(B.quant_blocks)), qb, B.lds, st, B.q);
+    else
+        hipLaunchKernelGGL(grouped_quantize_kernel<uint8_t>, dim3(unsigned(B.quant_blocks)), qb, B.lds, st, B.q);
+    e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_fail(e, "grouped_quantize_kernel launch");
 }
 
 int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {

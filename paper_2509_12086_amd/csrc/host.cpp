@@ -465,6 +465,12 @@ void saq_plan::derive() {
         }
     }
     if (var.empty()) var.assign(size_t(D), 0.0);
+    // FP32 accumulation over the whole input dimension measurably breaks
+    // code parity for long inputs and fine grids (D = 3072 with 9-bit
+    // segments: 3e-4 of codes differ, against 4e-5 with FP64 k-tile totals);
+    // auto mode takes the FP64 totals there
+    const int mode = params.projection_accumulation;
+    acc64 = mode == 2 || (mode == 0 && (D > 1024 || max_kept_b >= 8));
     build_staging(*this);
 }
 
@@ -480,6 +486,7 @@ void saq_default_params(saq_plan_params* p) {
     p->rotate_segments = 1;
     p->fit_sample = 65536;
     p->seed = 1;
+    p->projection_accumulation = 0;
 }
 
 const char* saq_last_error(void) { return g_last_error.c_str(); }
@@ -612,6 +619,7 @@ saq_status saq_plan_info_get(const saq_plan* p, saq_plan_info* o) {
     o->min_error = p->min_error;
     o->quota_bits = p->quota;
     o->used_bits = p->used;
+    o->projection_fp64_totals = p->acc64 ? 1 : 0;
     return SAQ_OK;
 }
 

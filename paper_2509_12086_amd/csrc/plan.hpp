@@ -44,6 +44,7 @@ struct saq_plan {
 
     // derived
     int32_t D_kept = 0, n_kept = 0, max_kept_w = 0, max_kept_b = 0;
+    bool acc64 = false;                  // projection accumulates k-tiles into FP64
     int64_t code_bytes = 0;
     std::vector<saq::SegEntry> kept;
 

@@ -1,0 +1,120 @@
+"""Batched encode (many datasets with uneven segments in two grouped
+launches): every dataset's records are bit-identical to its own plain
+saq_encode, for every launch shape the autotuner may pick."""
+import numpy as np
+import pytest
+
+import synth
+import paper_2509_12086_amd as saq
+from paper_2509_12086_amd import autotune
+from gpu_util import compare, cuda, oracle_encode, say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _basis_plan(ds, bpd, **kw):
+    """Plan from the generating basis (rotation columns, spectrum)."""
+    return saq.Plan.from_basis(np.zeros(ds.d), ds.rotation, ds.lam,
+                               saq.PlanParams(bits_per_dim=bpd, **kw)).upload(0)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    sets = []
+    ds = synth.cfg1(6000)
+    X = ds.rows()
+    sets.append((saq.Plan.fit(X, saq.PlanParams(bits_per_dim=4.0, fit_sample=0)).upload(0), X))
+    ds = synth.cfg4(3000)
+    sets.append((_basis_plan(ds, 6.0), ds.rows()))
+    rng = np.random.default_rng(99)
+    X = (rng.standard_normal((777, 99)) * np.exp(-np.arange(99) / 30.0)).astype(np.float32)
+    sets.append((saq.Plan.fit(X, saq.PlanParams(bits_per_dim=2.0, granularity=8, max_width=32,
+                                               fit_sample=0)).upload(0), X))
+    ds = synth.cfg3(0, 1500)
+    sets.append((_basis_plan(ds, 8.0), ds.rows()))
+    ds = synth.cfg5(0, 1)
+    sets.append((_basis_plan(ds, 3.0), ds.rows()))
+    say("batch plans: " + "; ".join(f"D={p.D} W={p.kept_widths} B={p.kept_bits}" for p, _ in sets))
+    return [(p, to_dev(X)) for p, X in sets]
+
+
+def _plain(batch, rounds):
+    out = []
+    for p, X in batch:
+        c, f = saq.encode(p, X, rounds)
+        out.append((c, f))
+    torch.cuda.synchronize()
+    return [(c.cpu().numpy(), f.cpu().numpy()) for c, f in out]
+
+
+@pytest.mark.parametrize("tuning", [
+    saq.BatchTuning(),
+    saq.BatchTuning(quant_waves=2, gemm_xcd_order=False),
+    saq.BatchTuning(quant_waves=4, gemm_xcd_order=True),
+])
+def test_batched_bit_identical_to_plain(batch, tuning):
+    say(f"batched encode {tuning}")
+    ref = _plain(batch, 4)
+    ws = torch.empty(saq.batched_workspace_bytes(batch, tuning), dtype=torch.uint8, device=cuda())
+    outs = saq.encode_batched(batch, 4, tuning, ws)
+    torch.cuda.synchronize()
+    for (c, f), (rc, rf), (p, _) in zip(outs, ref, batch):
+        assert np.array_equal(c.cpu().numpy(), rc), p.D
+        assert np.array_equal(f.cpu().numpy(), rf), p.D
+
+
+def test_batched_with_empty_entry_and_rounds(batch):
+    empty = (batch[0][0], batch[0][1][:0])
+    sub = [batch[1], empty, batch[4]]
+    for rounds in (0, 1, 7):
+        ref = _plain([batch[1], batch[4]], rounds)
+        outs = saq.encode_batched(sub, rounds)
+        torch.cuda.synchronize()
+        assert outs[1][0].shape[0] == 0
+        for (c, f), (rc, rf) in zip([outs[0], outs[2]], ref):
+            assert np.array_equal(c.cpu().numpy(), rc) and np.array_equal(f.cpu().numpy(), rf)
+
+
+def test_batched_matches_oracle_wide_segments(batch):
+    """The D=3072, 8 b/dim plan has 9-bit segments up to 512 wide (16-bit
+    codes, one wave per quantize workgroup): compare with the oracle too."""
+    p, X = batch[3]
+    X = X[:300].contiguous()
+    outs = saq.encode_batched([(p, X)], 4)
+    torch.cuda.synchronize()
+    c, f = outs[0]
+    compare(p, c.cpu().numpy(), f.cpu().numpy(), oracle_encode(p, X.cpu().numpy(), 4),
+            label="batched D3072 b8")
+
+
+def test_batched_argument_errors(batch):
+    with pytest.raises(ValueError):
+        saq.encode_batched([batch[0]] * 17)
+    p, X = batch[0]
+    small = torch.empty(64, dtype=torch.uint8, device=cuda())
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p, X)], 4, workspace=small)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p, X)], -2)
+
+
+def test_autotuner_picks_a_valid_shape(batch):
+    best, table = autotune.tune(batch[:3], rounds=4, reps=1, sample_rows=4096)
+    assert len(table) == len(autotune.candidates())
+    assert best in [t for t, _ in table]
+    again, table2 = autotune.tune(batch[:3], rounds=4)
+    assert again == best and table2 == []           # cached
+    outs = saq.encode_batched(batch[:3], 4, best)
+    torch.cuda.synchronize()
+    for (c, f), (rc, rf) in zip(outs, _plain(batch[:3], 4)):
+        assert np.array_equal(c.cpu().numpy(), rc) and np.array_equal(f.cpu().numpy(), rf)
+
+
+@pytest.mark.skip(reason="the single persistent launch with in-kernel waits between projection "
+                         "and quantize work items did not finish on the GPU (twice); its cause "
+                         "could not be shown on the CPU (a CPU model of its queue protocol is "
+                         "deadlock-free), so that code path was removed and the batch runs as "
+                         "two grouped launches instead")
+def test_persistent_single_launch_pipeline():
+    raise AssertionError("removed code path")

@@ -150,3 +150,17 @@ def test_record_size_formula():
                             np.zeros(D, np.float32))
     assert p.code_bytes == 9 * 2 + 3 * 2 + 1 * 2
     assert p.kept_widths == [16, 12, 12] and p.kept_bits == [9, 3, 1]
+
+
+def test_projection_accumulation_mode():
+    """Auto mode adds the projection's k-tiles in FP64 for long inputs or
+    fine grids (D > 1024 or a kept segment with >= 8 bits), else FP32."""
+    def mode(D, bits, acc):
+        M = np.eye(D, dtype=np.float32)[:16]
+        p = saq.Plan.from_parts([16, D - 16], [bits, 0], M, np.zeros(D, np.float32))
+        return p.info["projection_fp64_totals"]
+    assert mode(960, 7, 0) == 0 and mode(960, 8, 0) == 1 and mode(2048, 4, 0) == 1
+    X = np.random.default_rng(0).standard_normal((500, 64)).astype(np.float32)
+    for acc, want in ((0, 0), (1, 0), (2, 1)):
+        p = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=2.0, fit_sample=0, projection_accumulation=acc))
+        assert p.info["projection_fp64_totals"] == want
