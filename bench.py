@@ -44,6 +44,9 @@ def parse():
                     help="length of the served-ingestion trace (0 = skip)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel loops (short runs under a profiler)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (calibrates the "
+                         "profiler's byte counters)")
     return ap.parse_args()
 
 
@@ -116,6 +119,14 @@ def main():
                                                      saq.LAYOUT_DIMS, n, stream), a.steps)
     if ms_step is None:
         ms_step = proj_ms + quant_ms
+    if a.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)          # reads 1 GiB, writes 1 GiB per call
+        torch.cuda.synchronize()
+        del src, dst
 
     flops = 2.0 * D * dk * n
     proj_tflops = flops / (proj_ms * 1e-3) / 1e12

@@ -49,8 +49,8 @@ constexpr int GEMM_LDS_FLOATS = 2 * (TM + TN) * LDS_STRIDE;   // 73,728 bytes
 
 // One 128 x 128 output tile (tile_m, tile_n).  lds: GEMM_LDS_FLOATS floats,
 // free on entry and on return (the last k-step ends with a barrier).
-template <int LAYOUT, bool ACC64>
-__device__ __forceinline__ void gemm_tile(
+template <int LAYOUT, bool ACC64, bool NORM>
+__device__ __forceinline__ void gemm_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
     float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
@@ -67,7 +67,6 @@ __device__ __forceinline__ void gemm_tile(
     // rows past n read row n-1 (always valid memory) and are zeroed on store
     const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
     const float* brow = Mp + int64_t(n0 + lr) * k_pad;
-    const bool do_norm = (norm2 != nullptr) && tile_n == 0;
     double nacc = 0.0;
 
     // raw global values of the next tile; consumed only after the MFMAs of
@@ -94,14 +93,15 @@ __device__ __forceinline__ void gemm_tile(
             rb[e] = brow[kb + e];
         }
     };
+    // rows past n hold row n-1: their outputs and norms are never stored
     auto store_tile = [&](int buf) {
         float ra[16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            ra[e] = arow_ok ? rx[e] - rc[e] : 0.f;
-            if (do_norm) {
+            ra[e] = rx[e] - rc[e];
+            if (NORM) {
                 // exact (x - c)^2 in FP64; padding entries are 0 - 0
-                const double d = arow_ok ? double(rx[e]) - double(rc[e]) : 0.0;
+                const double d = double(rx[e]) - double(rc[e]);
                 nacc = fma(d, d, nacc);
             }
         }
@@ -184,7 +184,7 @@ __device__ __forceinline__ void gemm_tile(
         __syncthreads();
     }
 
-    if (do_norm) {
+    if (NORM) {
         nacc += __shfl_xor(nacc, 1);
         if ((t & 1) == 0 && arow_ok) norm2[arow] = float(nacc);
     }
@@ -228,6 +228,21 @@ __device__ __forceinline__ void gemm_tile(
                 }
             }
         }
+}
+
+// ||x - c||^2 is produced by the first column tile only; the k-loop is
+// specialised so the other tiles carry none of its work.
+template <int LAYOUT, bool ACC64>
+__device__ __forceinline__ void gemm_tile(
+    bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
+    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
+    if (norm2 != nullptr && tile_n == 0)
+        gemm_tile_impl<LAYOUT, ACC64, true>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
+                                            tile_n, lds);
+    else
+        gemm_tile_impl<LAYOUT, ACC64, false>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
+                                             tile_n, lds);
 }
 
 template <bool VEC, int LAYOUT, bool ACC64>
