@@ -78,8 +78,7 @@ def main():
     codes = torch.empty((n, plan.code_bytes), dtype=torch.uint8, device=dev)
     fac = torch.empty((n, plan.n_factors), dtype=torch.float32, device=dev)
     ws = torch.empty(plan.encode_workspace_bytes(n), dtype=torch.uint8, device=dev)
-    ld = (n + 3) // 4 * 4
-    O = torch.empty((max(dk, 1), ld), dtype=torch.float32, device=dev)
+    O = torch.empty(((n + 63) // 64, max(dk, 1), 64), dtype=torch.float32, device=dev)
     nrm = torch.empty(n, dtype=torch.float32, device=dev)
 
     def step():
@@ -113,10 +112,10 @@ def main():
         d = [evs[i].elapsed_time(evs[i + 1]) for i in range(k)]
         return float(np.mean(d)), float(np.min(d))
 
-    proj_ms, proj_min = timed(lambda: saq.project(plan, X, O, nrm, saq.LAYOUT_DIMS, stream),
+    proj_ms, proj_min = timed(lambda: saq.project(plan, X, O, nrm, saq.LAYOUT_TILES, stream),
                               a.steps)
     quant_ms, quant_min = timed(lambda: saq.quantize(plan, O, a.rounds, nrm, codes, fac,
-                                                     saq.LAYOUT_DIMS, n, stream), a.steps)
+                                                     saq.LAYOUT_TILES, n, stream), a.steps)
     if ms_step is None:
         ms_step = proj_ms + quant_ms
     if a.copy_probe:

@@ -141,12 +141,20 @@ saq_status saq_encode(const saq_plan* plan, const float* X_dev, int64_t n, int32
                       void* stream);
 
 /* Layouts of a projected-row buffer O with leading dimension ld:
-   SAQ_LAYOUT_ROWS: element (vector i, kept dim j) at O[i * ld + j], ld >= D_kept
-   SAQ_LAYOUT_DIMS: element (vector i, kept dim j) at O[j * ld + i], ld >= n,
-                    ld % 4 == 0 and O 16-byte aligned (what saq_encode uses
-                    internally: one coalesced row per kept dim) */
-#define SAQ_LAYOUT_ROWS 0
-#define SAQ_LAYOUT_DIMS 1
+   SAQ_LAYOUT_ROWS:  element (vector i, kept dim j) at O[i * ld + j], ld >= D_kept
+   SAQ_LAYOUT_DIMS:  element (vector i, kept dim j) at O[j * ld + i], ld >= n,
+                     ld % 4 == 0 and O 16-byte aligned
+   SAQ_LAYOUT_TILES: element (vector i, kept dim j) at
+                     O[((i / 64) * ld + j) * 64 + i % 64], ld >= D_kept, O
+                     16-byte aligned and holding ceil(n / 64) whole tiles of
+                     ld x 64 floats (what saq_encode uses internally: the 64
+                     vectors one wave quantizes are one tile, each kept dim 64
+                     contiguous floats).  saq_project also fills the slots of
+                     the last tile past n (with copies of row n - 1);
+                     saq_quantize reads them and never uses their values. */
+#define SAQ_LAYOUT_ROWS  0
+#define SAQ_LAYOUT_DIMS  1
+#define SAQ_LAYOUT_TILES 2
 
 /* The projection step alone (the GEMM saq_encode runs):
    O = M (x_i - c) for the D_kept kept dims in the given layout, and

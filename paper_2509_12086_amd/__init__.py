@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libsaq.so")
 
 LAYOUT_ROWS = 0
 LAYOUT_DIMS = 1
+LAYOUT_TILES = 2
 
 _STATUS = {0: "SAQ_OK", 1: "SAQ_EINVAL", 2: "SAQ_ENOMEM", 3: "SAQ_EDEVICE",
            4: "SAQ_EUNSUPPORTED", 5: "SAQ_EIO"}
@@ -277,12 +278,12 @@ class Plan:
         return int(lib().saq_estimate_workspace_bytes(self._h, nq))
 
 
-def _require_cuda_f32(t, name, cols=None):
+def _require_cuda_f32(t, name, cols=None, ndim=2):
     torch = _torch()
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32):
         raise TypeError(f"{name} must be a CUDA float32 tensor")
-    if t.dim() != 2 or not t.is_contiguous():
-        raise ValueError(f"{name} must be a contiguous 2-D tensor")
+    if t.dim() != ndim or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {ndim}-D tensor")
     if cols is not None and t.shape[1] != cols:
         raise ValueError(f"{name} has {t.shape[1]} columns, expected {cols}")
 
@@ -315,35 +316,47 @@ def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=N
     return codes, factors
 
 
+def _layout_ld(O, layout: int) -> int:
+    if layout == LAYOUT_TILES:
+        if O.dim() != 3 or O.shape[2] != 64 or not O.is_contiguous():
+            raise ValueError("the tiled layout takes a contiguous [tiles, ld, 64] tensor")
+        return O.shape[1]
+    return O.stride(0)
+
+
 def project(plan: Plan, X, out=None, norm2=None, layout: int = LAYOUT_ROWS, stream=None):
     """saq_project: (O f32, ||x - c||^2 f32 [n]).  Row layout: O [n, >= D_kept];
-    dims layout: O [D_kept, ld >= n] with ld % 4 == 0."""
+    dims layout: O [D_kept, ld >= n] with ld % 4 == 0; tiled layout: O
+    [ceil(n / 64), ld >= D_kept, 64]."""
     torch = _torch()
     _require_cuda_f32(X, "X", plan.D)
     n = X.shape[0]
     if out is None:
-        shape = (n, max(plan.D_kept, 1)) if layout == LAYOUT_ROWS else \
-            (max(plan.D_kept, 1), (n + 3) // 4 * 4)
+        dk = max(plan.D_kept, 1)
+        shape = {LAYOUT_ROWS: (n, dk), LAYOUT_DIMS: (dk, (n + 3) // 4 * 4),
+                 LAYOUT_TILES: ((n + 63) // 64, dk, 64)}[layout]
         out = torch.empty(shape, dtype=torch.float32, device=X.device)
     if norm2 is None:
         norm2 = torch.empty(n, dtype=torch.float32, device=X.device)
-    _check(lib().saq_project(plan._h, _dev_ptr(X), n, _dev_ptr(out), out.stride(0), layout,
-                             _dev_ptr(norm2), _stream_ptr(stream, X.device)))
+    _check(lib().saq_project(plan._h, _dev_ptr(X), n, _dev_ptr(out), _layout_ld(out, layout),
+                             layout, _dev_ptr(norm2), _stream_ptr(stream, X.device)))
     return out, norm2
 
 
 def quantize(plan: Plan, O, rounds: int = 4, norm2=None, codes=None, factors=None,
              layout: int = LAYOUT_ROWS, n: Optional[int] = None, stream=None):
-    """saq_quantize on projected rows O (row layout [n, >= D_kept], or dims
-    layout [D_kept, ld] with ``n`` given)."""
-    _require_cuda_f32(O, "O")
+    """saq_quantize on projected rows O (row layout [n, >= D_kept]; dims
+    layout [D_kept, ld] or tiled layout [tiles, ld, 64] with ``n`` given)."""
+    _require_cuda_f32(O, "O", ndim=3 if layout == LAYOUT_TILES else 2)
     if n is None:
         if layout != LAYOUT_ROWS:
-            raise ValueError("n is required for the dims layout")
+            raise ValueError("n is required for the dims and tiled layouts")
         n = O.shape[0]
+    if layout == LAYOUT_TILES and O.shape[0] * 64 < n:
+        raise ValueError("tiled O holds fewer than n vectors")
     codes, factors = _alloc_out(plan, n, O.device, codes, factors)
-    _check(lib().saq_quantize(plan._h, _dev_ptr(O), O.stride(0), layout, n, _dev_ptr(norm2),
-                              rounds, _dev_ptr(codes), _dev_ptr(factors),
+    _check(lib().saq_quantize(plan._h, _dev_ptr(O), _layout_ld(O, layout), layout, n,
+                              _dev_ptr(norm2), rounds, _dev_ptr(codes), _dev_ptr(factors),
                               _stream_ptr(stream, O.device)))
     return codes, factors
 

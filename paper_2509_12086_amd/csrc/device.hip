@@ -17,6 +17,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "plan.hpp"
 
@@ -32,7 +33,7 @@ constexpr int TK = saq::kGemmTileK;   // 32 input dims per k-step
 constexpr int LDS_STRIDE = TK + 4;    // floats per LDS row (conflict-free b128 reads)
 constexpr int NXCD = 8;               // MI355X: 8 XCDs, workgroups dealt round-robin
 
-enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1 };
+enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1, LAYOUT_TILES = 2 };
 
 // ---------------------------------------------------------------------------
 // Projection GEMM.  Workgroup = 256 threads (4 waves) computes a 128 x 128
@@ -210,7 +211,14 @@ __device__ __forceinline__ void gemm_tile_impl(
                     v0 = acc[bi][bj][4 * g + 0]; v1 = acc[bi][bj][4 * g + 1];
                     v2 = acc[bi][bj][4 * g + 2]; v3 = acc[bi][bj][4 * g + 3];
                 }
-                if (LAYOUT == LAYOUT_DIMS) {
+                if (LAYOUT == LAYOUT_TILES) {
+                    // whole 64-row tiles: rows of the last tile past n (copies
+                    // of row n-1) are stored too
+                    if (row < ((n + 63) & ~int64_t(63))) {
+                        float* dst = O + ((row >> 6) * ld + col) * 64 + (row & 63);
+                        *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+                    }
+                } else if (LAYOUT == LAYOUT_DIMS) {
                     float* dst = O + int64_t(col) * ld + row;
                     if (row + 3 < n) {
                         *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
@@ -260,9 +268,10 @@ __global__ __launch_bounds__(256) void project_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Quantize + adjust + factor + pack.  One wave (64 lanes) per block, one
-// vector per lane; the block's 64 codes of the current segment live in LDS
-// as [dim][lane] (conflict-free), the projected values stream from O.
+// Quantize + adjust + factor + pack.  One wave (64 lanes) per 64 vectors, one
+// vector per lane; the wave's 64 codes of the current segment live in LDS as
+// [dim][lane] (conflict-free), the projected values stream from O in chunks
+// of QCH dims, the next chunk in flight while the current one is used.
 //
 // Adjustment decision (Algorithm 1, "L(x') > L(x)"), exact reformulation:
 // with u = code - (2^B-1)/2, ip = <u,o>, n = ||u||^2 and a move u_i += s,
@@ -277,10 +286,130 @@ __global__ __launch_bounds__(256) void project_kernel(
 // A round that accepts nothing leaves the state unchanged, so once no lane
 // of the wave accepted anything the remaining rounds are skipped.
 // ---------------------------------------------------------------------------
-constexpr int QCH = 8;   // dims per prefetch chunk in the quantize kernel
+constexpr int QCH = 16;   // dims per prefetch chunk in the quantize kernel
 
-// One wave quantizes vectors v0 .. v0+63 (one per lane).  lc: this wave's
-// code buffer, [max kept width][64] entries (LDS or global memory).
+// Where one lane's projected values sit.  Tiled layout: the 64 vectors of a
+// wave are one tile, dim j of the tile 64 contiguous floats, so a chunk is
+// QCH loads at immediate offsets from one wave-uniform base.
+template <int LAYOUT>
+struct LaneView {
+    const float* p;   // kept dim 0 of this lane's vector
+    int64_t sd;       // elements between consecutive dims (row and dims layouts)
+
+    __device__ __forceinline__ int64_t stride() const { return LAYOUT == LAYOUT_TILES ? 64 : sd; }
+
+    // dims j0 .. j0+QCH-1 of the segment starting at kept dim col; dims past
+    // its width W are clamped to its last dim (loaded, never used)
+    __device__ __forceinline__ void load(float (&dst)[QCH], int col, int j0, int W) const {
+        const float* q = p + int64_t(col + j0) * stride();
+        if (j0 + QCH <= W) {
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) dst[t] = q[int64_t(t) * stride()];
+        } else {
+            const int last = W - 1 - j0;
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) dst[t] = q[int64_t(min(t, last)) * stride()];
+        }
+    }
+};
+
+// One in-order pass over the W dims of a segment: body(x, i0, full) for every
+// chunk, full = std::true_type when all QCH dims of the chunk are inside the
+// segment.  On entry a holds chunk 0; on return a holds chunk 0 again,
+// loaded during the last chunk for the pass that follows.
+template <int LAYOUT, class Body>
+__device__ __forceinline__ void sweep(const LaneView<LAYOUT>& lv, int col, int W,
+                                      float (&a)[QCH], float (&b)[QCH], Body&& body) {
+    auto run = [&](const float (&x)[QCH], int i0) {
+        if (i0 + QCH <= W) body(x, i0, std::true_type{});
+        else body(x, i0, std::false_type{});
+    };
+    for (int i0 = 0;;) {
+        const bool more = i0 + QCH < W;
+        lv.load(b, col, more ? i0 + QCH : 0, W);
+        run(a, i0);
+        i0 += QCH;
+        if (!more) {
+#pragma unroll
+            for (int t = 0; t < QCH; ++t) a[t] = b[t];
+            return;
+        }
+        const bool more2 = i0 + QCH < W;
+        lv.load(a, col, more2 ? i0 + QCH : 0, W);
+        run(b, i0);
+        i0 += QCH;
+        if (!more2) return;
+    }
+}
+
+// Bit planes of one segment, most significant first; dim i -> byte i/8,
+// bit i%8 of the plane.  Built 32 dims at a time into one word per plane and
+// stored as whole 32-bit words when every plane of the segment is 4-byte
+// aligned in memory, else as 16-bit halves, else bytes.
+template <typename CT, int B>
+__device__ __forceinline__ void pack_planes(const CT* __restrict__ lc, int W, int lane,
+                                            uint8_t* __restrict__ dst0, int pb, int unit,
+                                            bool live) {
+    for (int j0 = 0; j0 < W; j0 += 32) {
+        uint32_t word[B];
+#pragma unroll
+        for (int p = 0; p < B; ++p) word[p] = 0u;
+        if (j0 + 32 <= W) {
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                const uint32_t c = uint32_t(lc[(j0 + t) * 64 + lane]);
+#pragma unroll
+                for (int p = 0; p < B; ++p) word[p] |= ((c >> p) & 1u) << t;
+            }
+        } else {
+            for (int t = 0; j0 + t < W; ++t) {
+                const uint32_t c = uint32_t(lc[(j0 + t) * 64 + lane]);
+#pragma unroll
+                for (int p = 0; p < B; ++p) word[p] |= ((c >> p) & 1u) << t;
+            }
+        }
+        if (!live) continue;
+        const int nb = min(4, pb - (j0 >> 3));   // bytes of this word inside the plane
+#pragma unroll
+        for (int p = 0; p < B; ++p) {
+            uint8_t* dst = dst0 + int64_t(B - 1 - p) * pb + (j0 >> 3);
+            const uint32_t w = word[p];
+            if (unit == 4) {
+                *reinterpret_cast<uint32_t*>(dst) = w;
+            } else if (unit == 2) {
+                reinterpret_cast<uint16_t*>(dst)[0] = uint16_t(w);
+                if (nb > 2) reinterpret_cast<uint16_t*>(dst)[1] = uint16_t(w >> 16);
+            } else {
+                for (int k = 0; k < nb; ++k) dst[k] = uint8_t(w >> (8 * k));
+            }
+        }
+    }
+}
+
+template <typename CT>
+__device__ __forceinline__ void pack_segment(const CT* __restrict__ lc, int W, int B, int lane,
+                                             uint8_t* __restrict__ dst0, int pb, int unit,
+                                             bool live) {
+    switch (B) {
+#define SAQ_PACK_CASE(K) \
+    case K: pack_planes<CT, K>(lc, W, lane, dst0, pb, unit, live); break;
+        SAQ_PACK_CASE(1) SAQ_PACK_CASE(2) SAQ_PACK_CASE(3) SAQ_PACK_CASE(4)
+        SAQ_PACK_CASE(5) SAQ_PACK_CASE(6) SAQ_PACK_CASE(7) SAQ_PACK_CASE(8)
+        default:
+            if constexpr (sizeof(CT) > 1) {
+                switch (B) {
+                    SAQ_PACK_CASE(9) SAQ_PACK_CASE(10) SAQ_PACK_CASE(11) SAQ_PACK_CASE(12)
+                    SAQ_PACK_CASE(13) SAQ_PACK_CASE(14) SAQ_PACK_CASE(15) SAQ_PACK_CASE(16)
+                    default: break;
+                }
+            }
+            break;
+#undef SAQ_PACK_CASE
+    }
+}
+
+// One wave quantizes vectors v0 .. v0+63 (one per lane; v0 % 64 == 0).
+// lc: this wave's code buffer, [max kept width][64] entries of LDS.
 template <typename CT, int LAYOUT>
 __device__ __forceinline__ void quantize_wave(
     const float* __restrict__ O, int64_t ld, int64_t n, int64_t v0, int lane,
@@ -290,150 +419,111 @@ __device__ __forceinline__ void quantize_wave(
     const int64_t v = v0 + lane;
     const bool live = v < n;
     const int64_t vv = live ? v : n - 1;
-    // element (vector vv, kept dim j)
-    const int64_t sv = LAYOUT == LAYOUT_DIMS ? 1 : ld;
-    const int64_t sd = LAYOUT == LAYOUT_DIMS ? ld : 1;
-    const float* ov = O + vv * sv;
+    LaneView<LAYOUT> lv;
+    if (LAYOUT == LAYOUT_TILES) {
+        // lanes past n read their own slots of the last tile (never used)
+        lv.p = O + (v0 >> 6) * ld * 64 + lane;
+        lv.sd = 64;
+    } else {
+        lv.p = O + (LAYOUT == LAYOUT_DIMS ? vv : vv * ld);
+        lv.sd = LAYOUT == LAYOUT_DIMS ? ld : 1;
+    }
     uint8_t* rec = codes + vv * code_bytes;
     double kept_norm = 0.0;
+    float a[QCH], b[QCH];
 
     for (int s = 0; s < n_kept; ++s) {
         const SegEntry e = segs[s];
-        const int W = e.width, B = e.bits;
+        const int W = e.width, B = e.bits, col = e.col;
         const int cmax = (1 << B) - 1;
-        const float* os = ov + int64_t(e.col) * sd;
-        // chunk loader: QCH consecutive dims starting at i0, indices past the
-        // segment clamped to its last dim (loaded, never used)
-        auto load = [&](float* dst, int i0) {
-#pragma unroll
-            for (int t = 0; t < QCH; ++t) dst[t] = os[int64_t(min(i0 + t, W - 1)) * sd];
-        };
-        float cur[QCH], nxt[QCH];
+        lv.load(a, col, 0, W);
 
-        // v_max = max |o_i| (exact in FP32) and ||o_s||^2 (FP64)
+        // v_max = max |o_i| (exact in FP32)
         float vmax = 0.f;
-        double oo = 0.0;
-        load(cur, 0);
-        for (int i0 = 0; i0 < W; i0 += QCH) {
-            load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+        sweep(lv, col, W, a, b, [&](const float (&x)[QCH], int i0, auto full) {
 #pragma unroll
             for (int t = 0; t < QCH; ++t)
-                if (i0 + t < W) {
-                    vmax = fmaxf(vmax, fabsf(cur[t]));
-                    oo = fma(double(cur[t]), double(cur[t]), oo);
-                }
-#pragma unroll
-            for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
-        }
-        kept_norm += oo;
+                if (decltype(full)::value || i0 + t < W) vmax = fmaxf(vmax, fabsf(x[t]));
+        });
         const bool zero = !(vmax > 0.f);
 
-        // initial code: c = floor((o + v) / Delta), Delta = 2 v / 2^B, clamped
-        // to 2^B - 1; computed as the exact floor (o + v and k * Delta are
-        // exact in FP64)
-        const double vd = double(vmax);
+        // initial code c = floor((o + v) / Delta), Delta = 2 v / 2^B, clamped to
+        // 2^B - 1.  a = o + v is exact in FP64 up to one rounding the CPU
+        // evaluation shares; q = floor(a / Delta) is taken from a * (1/Delta)
+        // and corrected by the exact remainder r = a - q Delta (exact in FP64
+        // for q >= 1, and r = a for q = 0).  An all-zero segment takes the
+        // middle code 2^(B-1) through v = 2^(B-1), Delta = 1.
+        const double vd = zero ? ldexp(1.0, B - 1) : double(vmax);
         const double delta = zero ? 1.0 : ldexp(2.0 * vd, -B);
-        const double inv = 1.0 / delta;
+        const double inv = zero ? 1.0 : ldexp(0.5 / vd, B);
         const double half = 0.5 * double(cmax);
-        double ip = 0.0, nn = 0.0;
-        for (int i0 = 0; i0 < W; i0 += QCH) {
-            load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+        double ip = 0.0, nn = 0.0, oo = 0.0;
+        sweep(lv, col, W, a, b, [&](const float (&x)[QCH], int i0, auto full) {
 #pragma unroll
             for (int t = 0; t < QCH; ++t) {
-                if (i0 + t >= W) continue;
-                const double o = double(cur[t]);
-                int c;
-                if (zero) {
-                    c = (cmax + 1) >> 1;
-                } else {
-                    const double a = o + vd;
-                    double q = floor(a * inv);
-                    if ((q + 1.0) * delta <= a) q += 1.0;
-                    if (q * delta > a) q -= 1.0;
-                    q = fmin(fmax(q, 0.0), double(cmax));
-                    c = int(q);
-                }
+                if (!(decltype(full)::value || i0 + t < W)) continue;
+                const double o = double(x[t]);
+                const double av = o + vd;
+                const double q = floor(av * inv);
+                const double r = fma(-q, delta, av);
+                int c = int(q) + (r >= delta ? 1 : 0) - (r < 0.0 ? 1 : 0);
+                c = min(max(c, 0), cmax);
                 lc[(i0 + t) * 64 + lane] = CT(c);
                 const double u = double(c) - half;
                 ip = fma(u, o, ip);
                 nn = fma(u, u, nn);
+                oo = fma(o, o, oo);
             }
-#pragma unroll
-            for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
-        }
+        });
+        kept_norm += oo;
 
-        // code adjustment (Algorithm 1); cur holds chunk 0 again here
+        // code adjustment (Algorithm 1)
         if (B >= 2 && rounds > 0) {
-            double P = 2.0 * ip, S = ip * ip;
+            const double cmd = double(cmax);
+            double P = 2.0 * ip, nS = -(ip * ip);
             for (int rd = 0; rd < rounds; ++rd) {
                 int moved = 0;
-                for (int i0 = 0; i0 < W; i0 += QCH) {
-                    load(nxt, i0 + QCH < W ? i0 + QCH : 0);
+                sweep(lv, col, W, a, b, [&](const float (&x)[QCH], int i0, auto full) {
+                    constexpr bool F = decltype(full)::value;
                     int cc[QCH];
 #pragma unroll
-                    for (int t = 0; t < QCH; ++t) cc[t] = int(lc[min(i0 + t, W - 1) * 64 + lane]);
+                    for (int t = 0; t < QCH; ++t)
+                        cc[t] = int(lc[(F ? i0 + t : min(i0 + t, W - 1)) * 64 + lane]);
 #pragma unroll
                     for (int t = 0; t < QCH; ++t) {
-                        if (i0 + t >= W) continue;
-                        const double o = double(cur[t]);
+                        if (!(F || i0 + t < W)) continue;
+                        const double o = double(x[t]);
                         const int c = cc[t];
-                        const double w = double(2 * c - cmax);          // 2u
+                        const double w = fma(2.0, double(c), -cmd);     // 2u, exact
                         // A = n o^2 - ip^2, Bv = 2 ip n o - ip^2 (2u):
                         //   +1 passes iff A + Bv > 0, -1 iff A - Bv > 0
                         const double no = nn * o;
-                        const double A = fma(no, o, -S);
-                        const double Bv = fma(no, P, -(S * w));
+                        const double A = fma(no, o, nS);
+                        const double Bv = fma(no, P, nS * w);
                         const bool up = c < cmax && Bv > -A;
-                        const bool dn = !up && c > 0 && A > Bv;
+                        const bool dn = c > 0 && A > Bv;   // taken only when up fails
                         if (up || dn) {
                             const double sg = up ? 1.0 : -1.0;
                             nn = nn + fma(sg, w, 1.0);      // (u + s)^2 = u^2 + 2su + 1
                             ip = fma(sg, o, ip);
                             P = 2.0 * ip;
-                            S = ip * ip;
+                            nS = -(ip * ip);
                             lc[(i0 + t) * 64 + lane] = CT(c + (up ? 1 : -1));
                             moved = 1;
                         }
                     }
-#pragma unroll
-                    for (int t = 0; t < QCH; ++t) cur[t] = nxt[t];
-                }
-                if (!__any(moved)) break;
+                });
+                if (!__any(moved && live)) break;
             }
         }
 
         // factor f_s = ||o_s||^2 / <u_s, o_s>
         if (live) factors[v * (n_kept + 1) + s] = zero ? 0.f : float(oo / ip);
 
-        // bit planes, most significant first; dim i -> byte i/8, bit i%8 of the
-        // plane.  Whole 32-bit words when every plane of the segment is
-        // 4-byte aligned, else 16-bit halves, else bytes.
         const int pb = (W + 7) >> 3;
         const int al = pb | e.code_off | int(code_bytes) | codes_align;
         const int unit = (al & 3) == 0 ? 4 : (al & 1) == 0 ? 2 : 1;
-        const int dims_per = unit * 8;
-        for (int j0 = 0; j0 < W; j0 += dims_per) {
-            uint32_t word[16];
-#pragma unroll
-            for (int p = 0; p < 16; ++p) word[p] = 0u;
-            for (int t = 0; t < dims_per && j0 + t < W; ++t) {
-                const uint32_t c = uint32_t(lc[(j0 + t) * 64 + lane]);
-#pragma unroll
-                for (int p = 0; p < 16; ++p)
-                    if (p < B) word[p] |= ((c >> p) & 1u) << t;
-            }
-            if (live) {
-                const int64_t byte0 = e.code_off + (j0 >> 3);
-#pragma unroll
-                for (int p = 0; p < 16; ++p) {
-                    if (p >= B) continue;
-                    uint8_t* dst = rec + byte0 + int64_t(B - 1 - p) * pb;
-                    if (unit == 4) *reinterpret_cast<uint32_t*>(dst) = word[p];
-                    else if (unit == 2) *reinterpret_cast<uint16_t*>(dst) = uint16_t(word[p]);
-                    else *dst = uint8_t(word[p]);
-                }
-            }
-        }
+        pack_segment<CT>(lc, W, B, lane, rec + e.code_off, pb, unit, live);
     }
     if (live) factors[v * (n_kept + 1) + n_kept] = norm2 ? norm2[v] : float(kept_norm);
 }
@@ -488,10 +578,10 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) 
     }
     if (tile_m >= S.tiles_m) return;
     if (S.acc64)
-        gemm_tile<LAYOUT_DIMS, ACC64>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
+        gemm_tile<LAYOUT_TILES, ACC64>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
                                       S.ld, S.norm2, tile_m, tile_n, lds);
     else
-        gemm_tile<LAYOUT_DIMS, false>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
+        gemm_tile<LAYOUT_TILES, false>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
                                       S.ld, S.norm2, tile_m, tile_n, lds);
 }
 
@@ -514,7 +604,7 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
     const int64_t v0 = (b - S.first_block) * 64 * waves + int64_t(wave) * 64;
     if (v0 >= S.n) return;
     CT* lc = reinterpret_cast<CT*>(smem) + int64_t(wave) * args.wmax * 64;
-    quantize_wave<CT, LAYOUT_DIMS>(S.O, S.ld, S.n, v0, lane, S.segs, S.n_kept, S.norm2,
+    quantize_wave<CT, LAYOUT_TILES>(S.O, S.ld, S.n, v0, lane, S.segs, S.n_kept, S.norm2,
                                    args.rounds, S.codes, S.code_bytes, S.codes_align,
                                    S.factors, lc);
 }
@@ -616,12 +706,16 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
     const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     if (layout == LAYOUT_DIMS && ((reinterpret_cast<uintptr_t>(O) & 15) != 0 || (ld % 4) != 0))
         return saq::fail(SAQ_EINVAL, "dims-major output needs a 16-byte aligned buffer and ld % 4 == 0");
+    if (layout == LAYOUT_TILES && (reinterpret_cast<uintptr_t>(O) & 15) != 0)
+        return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
 #define SAQ_LAUNCH_PROJ(V, L, A)                                                                  \
     hipLaunchKernelGGL((project_kernel<V, L, A>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),   \
                        p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n)
 #define SAQ_LAUNCH_PROJ2(V, L) \
     do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true); else SAQ_LAUNCH_PROJ(V, L, false); } while (0)
-    if (layout == LAYOUT_DIMS) {
+    if (layout == LAYOUT_TILES) {
+        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_TILES); else SAQ_LAUNCH_PROJ2(false, LAYOUT_TILES);
+    } else if (layout == LAYOUT_DIMS) {
         if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_DIMS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_DIMS);
     } else {
         if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_ROWS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_ROWS);
@@ -649,7 +743,9 @@ saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int la
 #define SAQ_LAUNCH_Q(CT, L)                                                                       \
     hipLaunchKernelGGL((quantize_kernel<CT, L>), grid, dim3(64), lds, st, O, ld, n, dev_seg(p),   \
                        p->n_kept, norm2, rounds, codes, p->code_bytes, codes_align, factors)
-    if (layout == LAYOUT_DIMS) {
+    if (layout == LAYOUT_TILES) {
+        if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_TILES); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_TILES);
+    } else if (layout == LAYOUT_DIMS) {
         if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_DIMS); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_DIMS);
     } else {
         if (small) SAQ_LAUNCH_Q(uint8_t, LAYOUT_ROWS); else SAQ_LAUNCH_Q(uint16_t, LAYOUT_ROWS);
@@ -659,8 +755,11 @@ saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int la
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "quantize_kernel launch");
 }
 
-// workspace of saq_encode: O (dims-major, [D_kept x ld]) then norm2 [n]
-int64_t enc_ld(int64_t n) { return round_up(std::max<int64_t>(n, 1), 4); }
+// workspace of saq_encode: O in the tiled layout ([ceil(n/64)][ld][64] with
+// ld = D_kept) then norm2 [n]
+int64_t enc_o_bytes(const saq_plan* p, int64_t n) {
+    return round_up(std::max<int64_t>(n, 1), 64) * std::max(p->D_kept, 1) * 4;
+}
 
 
 struct BatchPlan {
@@ -715,8 +814,8 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         const saq_batch_item& it = items[i];
         if (it.n == 0) continue;
         const saq_plan* p = it.plan;
-        const int64_t ld = enc_ld(it.n);
-        float* O = reinterpret_cast<float*>(base + take(int64_t(p->D_kept) * ld * 4));
+        const int64_t ld = std::max(p->D_kept, 1);
+        float* O = reinterpret_cast<float*>(base + take(enc_o_bytes(p, it.n)));
         float* nrm = reinterpret_cast<float*>(base + take(it.n * 4));
         GemmSet& G = B.g.set[B.g.count++];
         G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
@@ -761,7 +860,7 @@ saq_status saq_plan_upload(saq_plan* p, void* dev_buf, void* stream) {
 
 int64_t saq_encode_workspace_bytes(const saq_plan* p, int64_t n) {
     if (!p || n < 0) return -1;
-    return int64_t(p->D_kept) * enc_ld(n) * 4 + round_up(std::max<int64_t>(n, 1), 64) * 4 + 256;
+    return round_up(enc_o_bytes(p, n), 256) + round_up(std::max<int64_t>(n, 1), 64) * 4 + 256;
 }
 
 static saq_status check_layout(const saq_plan* p, int64_t n, int64_t ld, int32_t layout) {
@@ -769,6 +868,8 @@ static saq_status check_layout(const saq_plan* p, int64_t n, int64_t ld, int32_t
         if (ld < p->D_kept) return saq::fail(SAQ_EINVAL, "ld < D_kept for the row layout");
     } else if (layout == LAYOUT_DIMS) {
         if (ld < n || (ld % 4) != 0) return saq::fail(SAQ_EINVAL, "dims layout needs ld >= n and ld % 4 == 0");
+    } else if (layout == LAYOUT_TILES) {
+        if (ld < p->D_kept) return saq::fail(SAQ_EINVAL, "ld < D_kept for the tiled layout");
     } else {
         return saq::fail(SAQ_EINVAL, "unknown layout");
     }
@@ -805,15 +906,15 @@ saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t roun
     if (!X || !codes || !factors || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
     if (ws_bytes < saq_encode_workspace_bytes(p, n)) return saq::fail(SAQ_EINVAL, "workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t ld = enc_ld(n);
+    const int64_t ld = std::max(p->D_kept, 1);
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
     float* O = reinterpret_cast<float*>(base);
-    float* nrm = reinterpret_cast<float*>(base + int64_t(p->D_kept) * ld * 4);
+    float* nrm = reinterpret_cast<float*>(base + round_up(enc_o_bytes(p, n), 256));
     // with nothing kept the projection kernel still runs its first column
     // tile (all padding) to produce ||x - c||^2
-    saq_status s = launch_project(p, X, n, O, ld, LAYOUT_DIMS, nrm, st);
+    saq_status s = launch_project(p, X, n, O, ld, LAYOUT_TILES, nrm, st);
     if (s != SAQ_OK) return s;
-    return launch_quantize(p, O, ld, LAYOUT_DIMS, n, nrm, rounds, codes, factors, st);
+    return launch_quantize(p, O, ld, LAYOUT_TILES, n, nrm, rounds, codes, factors, st);
 }
 
 int64_t saq_encode_batched_workspace_bytes(const saq_batch_item* items, int32_t count,

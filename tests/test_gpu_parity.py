@@ -39,16 +39,22 @@ def test_projection_fp32_mfma(cfg1):
         M, c, _ = p.arrays()
         O, nn = saq.project(p, to_dev(Xs))
         Od, _ = saq.project(p, to_dev(Xs), layout=saq.LAYOUT_DIMS)
+        Ot, _ = saq.project(p, to_dev(Xs), layout=saq.LAYOUT_TILES)
         torch.cuda.synchronize()
-        O, nn, Od = O.cpu().numpy(), nn.cpu().numpy(), Od.cpu().numpy()
+        O, nn, Od, Ot = O.cpu().numpy(), nn.cpu().numpy(), Od.cpu().numpy(), Ot.cpu().numpy()
         ref, nref = oracle.project(Xs, M, c)
         err = np.abs(O[:, :p.D_kept] - ref)
         xn = np.sqrt(nref)[:, None]
         assert np.all(err <= D * U32 * xn * 1.01 + 1e-30)
         assert np.sqrt(np.mean(err ** 2)) <= 4 * U32 * np.sqrt(np.mean(nref))
         assert np.allclose(nn, nref, rtol=1e-6, atol=0)
-        # both output layouts come from the same accumulators
+        # all output layouts come from the same accumulators
         assert np.array_equal(Od[:p.D_kept, :n].T, O[:, :p.D_kept])
+        tiles = Ot.transpose(0, 2, 1).reshape(-1, Ot.shape[1])     # [tiles*64, ld]
+        assert np.array_equal(tiles[:n, :p.D_kept], O[:, :p.D_kept])
+        # the last tile's slots past n hold copies of row n - 1
+        pad = tiles[n:, :p.D_kept]
+        assert np.array_equal(pad, np.broadcast_to(O[n - 1, :p.D_kept], pad.shape))
 
 
 def test_quantize_projected_input_matches_exactly(cfg1):
@@ -67,6 +73,20 @@ def test_quantize_projected_input_matches_exactly(cfg1):
         rate = compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, max_rate=1e-6,
                        label=f"proj r={rounds}")
         assert rate == 0.0
+        # the dims-major and tiled layouts give the same bytes; the tiled
+        # buffer's slots past n hold NaN, which must not reach any output
+        n, dk = O32.shape[0], plan.D_kept
+        Od = np.zeros((dk, (n + 3) // 4 * 4), np.float32)
+        Od[:, :n] = O32.T
+        T = (n + 63) // 64
+        Ot = np.full((T * 64, dk + 3), np.nan, np.float32)
+        Ot[:n, :dk] = O32
+        Ot = np.ascontiguousarray(Ot.reshape(T, 64, dk + 3).transpose(0, 2, 1))
+        for layout, Ol in ((saq.LAYOUT_DIMS, Od), (saq.LAYOUT_TILES, Ot)):
+            c2, f2 = saq.quantize(plan, to_dev(Ol), rounds, norm2=to_dev(nn.astype(np.float32)),
+                                  layout=layout, n=n)
+            torch.cuda.synchronize()
+            assert torch.equal(c2, codes) and torch.equal(f2, fac), layout
 
 
 def test_quantize_projected_wide_bit_range():
