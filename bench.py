@@ -29,6 +29,28 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-ops/s
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "encode_1Mx960_b4_hbm_counters.md")
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain-copy calibration), or
+    None when the summary is for another workload or for other kernel
+    sources than the ones built here."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_RECORD).read()
+        rec = json.loads(text.split("<!-- traffic-record ", 1)[1].split(" -->", 1)[0])
+        src = b"".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f), "rb").read()
+                       for f in ("device.hip", "plan.hpp"))
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +150,8 @@ def main():
         del src, dst
 
     flops = 2.0 * D * dk * n
+    proj_bytes = n * (4.0 * D + 4.0 * dk + 4.0)        # read X, write O and ||x - c||^2
+    traffic_workload = f"{n:,} x {D}, {a.bpd:g} b/dim, r={a.rounds}"
     proj_tflops = flops / (proj_ms * 1e-3) / 1e12
     q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
     q_gbs = q_bytes / (quant_ms * 1e-3) / 1e9
@@ -171,8 +195,10 @@ def main():
             "peak": PEAK_FP32_MFMA / 1e12,
             "unit": "TFLOP/s",
             "frac": proj_tflops * 1e12 / PEAK_FP32_MFMA,
-            "traffic": None,
+            "traffic": recorded_traffic("project_kernel", traffic_workload),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
             "algorithmic_per_launch": flops,
+            "algorithmic_bytes_per_launch": proj_bytes,
             "avg_ms": proj_ms,
         },
         "quantize_kernel": {
@@ -183,6 +209,7 @@ def main():
             "unit": "GB/s",
             "frac": q_gbs * 1e9 / PEAK_HBM,
             "algorithmic_per_launch": q_bytes,
+            "traffic": recorded_traffic("quantize_kernel", traffic_workload),
             "avg_ms": quant_ms,
         },
         "end_to_end": {
