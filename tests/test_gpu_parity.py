@@ -71,7 +71,7 @@ def test_quantize_projected_input_matches_exactly(cfg1):
         codes, fac = saq.quantize(plan, to_dev(O32), rounds, norm2=to_dev(nn.astype(np.float32)))
         torch.cuda.synchronize()
         rate = compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, max_rate=1e-6,
-                       label=f"proj r={rounds}")
+                       label=f"proj r={rounds}", projected_input=True)
         assert rate == 0.0
         # the dims-major and tiled layouts give the same bytes; the tiled
         # buffer's slots past n hold NaN, which must not reach any output
@@ -108,7 +108,7 @@ def test_quantize_projected_wide_bit_range():
         codes, fac = saq.quantize(plan, to_dev(O), rounds)
         torch.cuda.synchronize()
         assert compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, max_rate=0,
-                       label=f"wide r={rounds}") == 0.0
+                       label=f"wide r={rounds}", projected_input=True) == 0.0
 
 
 def test_encode_cfg1_end_to_end(cfg1):
