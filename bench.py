@@ -64,6 +64,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="length of the served-ingestion trace (0 = skip)")
+    ap.add_argument("--batched-n", type=int, default=1_000_000,
+                    help="vectors per dataset in the batched leg (0 = skip)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched leg (short runs under a profiler)")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel loops (short runs under a profiler)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -85,6 +89,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.batched_only:
+        print(json.dumps({"batched": batched_leg(a)}), flush=True)
+        return
     ds = synth.cfg2(a.n)
     t0 = time.time()
     X = ds.rows_torch(a.n, dev)
@@ -160,10 +167,13 @@ def main():
     cpu = None
     if not a.no_cpu and not a.kernels_only:
         cpu = cpu_baseline(plan, X, a)
+    del X, O, ws, codes, fac
+    torch.cuda.empty_cache()
+    batched = None
+    if a.batched_n > 0 and not a.kernels_only:
+        batched = batched_leg(a)
     serving = None
     if a.serve_seconds > 0 and not a.kernels_only:
-        del X, O, ws, codes, fac
-        torch.cuda.empty_cache()
         serving = serve_leg(a)
 
     out = {
@@ -219,10 +229,119 @@ def main():
                                                   PEAK_FP32_MFMA / (2.0 * D * dk)),
         },
         "cpu_baseline": cpu,
+        "batched": batched,
         "serving": serving,
     }
     out["end_to_end"]["frac_of_binding"] = out["value"] / out["end_to_end"]["binding_roofline_vectors_per_s"]
     print(json.dumps(out), flush=True)
+
+
+def batched_leg(a):
+    """Batched uneven segments: 4 datasets of n x 3072 (variance (i+1)^-1.2,
+    random rotation, one dataset per budget 1/2/4/8 b/dim), encoded by the
+    two grouped launches of saq_encode_batched with the launch shape the
+    autotuner picks, against the plain encoder run once per dataset."""
+    import torch
+    import synth
+    import paper_2509_12086_amd as saq
+    from paper_2509_12086_amd import autotune
+    dev = torch.device("cuda", 0)
+    n = a.batched_n
+    budgets = (1.0, 2.0, 4.0, 8.0)
+    entries = []
+    for i, b in enumerate(budgets):
+        ds = synth.cfg3(i, n)
+        plan = saq.Plan.from_basis(np.zeros(ds.d), ds.rotation, ds.lam,
+                                   saq.PlanParams(bits_per_dim=b, granularity=16, max_bits=9,
+                                                  max_width=512)).upload(0)
+        X = ds.rows_torch(n, dev)
+        codes = torch.empty((n, plan.code_bytes), dtype=torch.uint8, device=dev)
+        fac = torch.empty((n, plan.n_factors), dtype=torch.float32, device=dev)
+        entries.append((plan, X, codes, fac))
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    print(f"# batched leg: {len(entries)} x {n} x 3072, plans "
+          + "; ".join(f"{b:g}b: {len(p.kept_widths)} kept segs W {min(p.kept_widths)}-"
+                      f"{max(p.kept_widths)} B {min(p.kept_bits)}-{max(p.kept_bits)}"
+                      for b, (p, *_) in zip(budgets, entries)), file=sys.stderr, flush=True)
+
+    def timed(fn, k, warm):
+        for _ in range(warm):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    steps = max(1, min(a.steps, 3))
+    # plain: one saq_encode per dataset, sharing one workspace
+    ws = torch.empty(max(p.encode_workspace_bytes(n) for p, *_ in entries), dtype=torch.uint8,
+                     device=dev)
+    plain_ms = timed(lambda: [saq.encode(p, X, a.rounds, c, f, ws, stream)
+                              for p, X, c, f in entries], steps, 1)
+    ref = [(c.clone(), f.clone()) for _, _, c, f in entries]
+    del ws
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    best, table = autotune.tune([(p, X) for p, X, _, _ in entries], rounds=a.rounds, reps=2)
+    tune_s = time.perf_counter() - t0
+    wsb = torch.empty(saq.batched_workspace_bytes(entries, best), dtype=torch.uint8, device=dev)
+    batched_ms = timed(lambda: saq.encode_batched(entries, a.rounds, best, wsb, stream), steps, 1)
+    identical = all(torch.equal(c, rc) and torch.equal(f, rf)
+                    for (_, _, c, f), (rc, rf) in zip(entries, ref))
+    flops = sum(2.0 * p.D * p.D_kept * n for p, *_ in entries)
+    del wsb, ref
+    torch.cuda.empty_cache()
+
+    # many small datasets: 16 slices of 8,192 rows (4 per plan); here the
+    # two grouped launches replace 32 plain ones
+    small_n = 8192
+    small = [(p, X[j * small_n:(j + 1) * small_n]) for p, X, _, _ in entries for j in range(4)]
+    small = [(p, X, torch.empty((small_n, p.code_bytes), dtype=torch.uint8, device=dev),
+              torch.empty((small_n, p.n_factors), dtype=torch.float32, device=dev))
+             for p, X in small]
+    ws = torch.empty(max(p.encode_workspace_bytes(small_n) for p, *_ in small), dtype=torch.uint8,
+                     device=dev)
+    s_plain = timed(lambda: [saq.encode(p, X, a.rounds, c, f, ws, stream)
+                             for p, X, c, f in small], 10, 2)
+    s_best, _ = autotune.tune([(p, X) for p, X, _, _ in small], rounds=a.rounds, reps=3)
+    wss = torch.empty(saq.batched_workspace_bytes(small, s_best), dtype=torch.uint8, device=dev)
+    s_batched = timed(lambda: saq.encode_batched(small, a.rounds, s_best, wss, stream), 10, 2)
+    del small, ws, wss
+    out = {
+        "workload": f"{len(entries)} datasets x {n} x 3072, variance (i+1)^-1.2, random rotation; "
+                    "budgets 1/2/4/8 b/dim (one per dataset), r=" + str(a.rounds),
+        "plans": [{"bits_per_dim": b, "kept_widths": p.kept_widths, "kept_bits": p.kept_bits,
+                   "segments": len(p.widths),
+                   "fp64_k_tile_totals": bool(p.info["projection_fp64_totals"])}
+                  for b, (p, *_) in zip(budgets, entries)],
+        "plain_vectors_per_s": len(entries) * n / (plain_ms * 1e-3),
+        "plain_ms": plain_ms,
+        "batched_vectors_per_s": len(entries) * n / (batched_ms * 1e-3),
+        "batched_ms": batched_ms,
+        "batched_over_plain": plain_ms / batched_ms,
+        "projection_tflops_batched": flops / (batched_ms * 1e-3) / 1e12,
+        "records_identical_to_plain": identical,
+        "small": {"datasets": 16, "rows_each": small_n,
+                  "plain_ms": s_plain, "batched_ms": s_batched,
+                  "plain_vectors_per_s": 16 * small_n / (s_plain * 1e-3),
+                  "batched_vectors_per_s": 16 * small_n / (s_batched * 1e-3),
+                  "batched_over_plain": s_plain / s_batched,
+                  "tuning": {"quant_waves": s_best.quant_waves,
+                             "gemm_xcd_order": s_best.gemm_xcd_order}},
+        "autotune": {"best": {"quant_waves": best.quant_waves,
+                              "gemm_xcd_order": best.gemm_xcd_order},
+                     "seconds": tune_s,
+                     "table_ms": [{"quant_waves": t.quant_waves, "gemm_xcd_order": t.gemm_xcd_order,
+                                   "ms": ms} for t, ms in table]},
+    }
+    del entries
+    torch.cuda.empty_cache()
+    return out
 
 
 def serve_leg(a):
