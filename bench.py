@@ -32,22 +32,41 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-ops/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "encode_1Mx960_b4_hbm_counters.md")
 
 
-def recorded_traffic(kernel: str, workload: str):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain-copy calibration), or
-    None when the summary is for another workload or for other kernel
-    sources than the ones built here."""
+def _record(path: str, tag: str, workload: str):
+    """The machine-readable record of a committed counter summary, or None
+    when it is for another workload or for other kernel sources than the
+    ones built here."""
     import hashlib
     try:
-        text = open(TRAFFIC_RECORD).read()
-        rec = json.loads(text.split("<!-- traffic-record ", 1)[1].split(" -->", 1)[0])
+        text = open(path).read()
+        rec = json.loads(text.split(f"<!-- {tag} ", 1)[1].split(" -->", 1)[0])
         src = b"".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f), "rb").read()
                        for f in ("device.hip", "plan.hpp"))
     except (OSError, IndexError, ValueError):
         return None
     if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    return rec
+
+
+INSTR_RECORD = os.path.join(ROOT, "profiles", "encode_1Mx960_b4_instruction_mix.md")
+
+
+def recorded_valu(kernel: str, workload: str):
+    """Wave-level VALU instructions per launch of `kernel` (rocprofv3
+    SQ_INSTS_VALU), under the same conditions as recorded_traffic."""
+    rec = _record(INSTR_RECORD, "instruction-record", workload)
+    k = None if rec is None else rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("SQ_INSTS_VALU")
+
+
+def recorded_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by a plain-copy calibration), or
+    None when the summary is for another workload or for other kernel
+    sources than the ones built here."""
+    rec = _record(TRAFFIC_RECORD, "traffic-record", workload)
+    k = None if rec is None else rec.get("kernels", {}).get(kernel)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
@@ -159,6 +178,7 @@ def main():
     flops = 2.0 * D * dk * n
     proj_bytes = n * (4.0 * D + 4.0 * dk + 4.0)        # read X, write O and ||x - c||^2
     traffic_workload = f"{n:,} x {D}, {a.bpd:g} b/dim, r={a.rounds}"
+    q_valu = recorded_valu("quantize_kernel", traffic_workload)
     proj_tflops = flops / (proj_ms * 1e-3) / 1e12
     q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
     q_gbs = q_bytes / (quant_ms * 1e-3) / 1e9
@@ -213,13 +233,14 @@ def main():
         },
         "quantize_kernel": {
             "kernel": "quantize_kernel (grid code, adjustment, factors, packing)",
-            "bound": "hbm",
-            "achieved": q_gbs,
-            "peak": PEAK_HBM / 1e9,
-            "unit": "GB/s",
-            "frac": q_gbs * 1e9 / PEAK_HBM,
-            "algorithmic_per_launch": q_bytes,
-            "traffic": recorded_traffic("quantize_kernel", traffic_workload),
+            "bound": "alu",
+            "hbm": {"achieved": q_gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": q_gbs * 1e9 / PEAK_HBM, "algorithmic_per_launch": q_bytes,
+                    "traffic": recorded_traffic("quantize_kernel", traffic_workload)},
+            "valu": None if q_valu is None else {
+                "achieved": q_valu * 64 / (quant_ms * 1e-3), "peak": VALU_LANE_OPS,
+                "unit": "lane-ops/s", "frac": q_valu * 64 / (quant_ms * 1e-3) / VALU_LANE_OPS,
+                "instructions_per_launch": q_valu},
             "avg_ms": quant_ms,
         },
         "end_to_end": {
