@@ -192,9 +192,10 @@ def main():
     batched = None
     if a.batched_n > 0 and not a.kernels_only:
         batched = batched_leg(a)
-    serving = None
+    serving = serving_mix = None
     if a.serve_seconds > 0 and not a.kernels_only:
         serving = serve_leg(a)
+        serving_mix = serve_mix_leg(a)
 
     out = {
         "metric": "SAQ encode vectors/s (D=960, 4 b/dim)" if a.bpd == 4.0 else
@@ -252,6 +253,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "serving": serving,
+        "serving_mix": serving_mix,
     }
     out["end_to_end"]["frac_of_binding"] = out["value"] / out["end_to_end"]["binding_roofline_vectors_per_s"]
     print(json.dumps(out), flush=True)
@@ -430,6 +432,75 @@ def serve_leg(a):
         "plain_encoder_vectors_per_s": plain,
         "max_queue": st["max_queue"],
     }
+
+
+def serve_mix_leg(a):
+    """Served multi-dataset mix: 8 resident datasets (D = 128, 128, 768, 768,
+    1536, 1536, 3072, 3072; variance exp(-8i/D); 4 b/dim plans), each with
+    1M stored records.  Poisson arrivals at 100 requests/s: 80 % encode
+    requests of log-uniform 1..131,072 vectors, 20 % estimate scans of 64
+    queries over the dataset's 1M stored records; datasets uniform; HBM
+    budget 64 GiB.  Latency runs from arrival to the results on the host."""
+    import torch
+    import synth
+    import paper_2509_12086_amd as saq
+    from paper_2509_12086_amd.serve import ENCODE, SCAN, GpuBackend, Server, replay
+    dev = torch.device("cuda", 0)
+    n_store, pool_n, rate = 1_000_000, 131_072, 100.0
+    be = GpuBackend(0, slots=4, rounds=a.rounds)
+    pools, queries = {}, {}
+    for i in range(len(synth.CFG5_DIMS)):
+        ds = synth.cfg5(i, n_store)
+        pid = f"d{i}"
+        plan = saq.Plan.from_basis(np.zeros(ds.d), ds.rotation, ds.lam,
+                                   saq.PlanParams(bits_per_dim=4.0)).upload(0)
+        be.add_plan(pid, plan)
+        X = ds.rows_torch(n_store, dev)
+        be.add_store(pid, *saq.encode(plan, X, a.rounds))
+        del X
+        pools[pid] = ds.rows_torch(pool_n, dev, seed_offset=1).cpu().pin_memory()
+        queries[pid] = ds.rows_torch(64, dev, seed_offset=2).cpu().pin_memory()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(52)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * a.serve_seconds * 1.5) + 10))
+    t = t[t < a.serve_seconds]
+    trace, offs = [], {pid: 0 for pid in pools}
+    for ti in t:
+        pid = f"d{rng.integers(len(pools))}"
+        if rng.random() < 0.2:
+            trace.append((float(ti), pid, queries[pid], SCAN))
+            continue
+        n = int(min(pool_n, max(1, round(np.exp(rng.uniform(0.0, np.log(pool_n)))))))
+        if offs[pid] + n > pool_n:
+            offs[pid] = 0
+        trace.append((float(ti), pid, pools[pid][offs[pid]:offs[pid] + n], ENCODE))
+        offs[pid] += n
+    budget = 64 << 30
+    warm = Server(be, hbm_budget=budget, keep_results=False).start()
+    for pid in pools:
+        warm.submit(pid, pools[pid][:1024])
+        warm.submit(pid, queries[pid], SCAN)
+    warm.drain()
+    server = Server(be, hbm_budget=budget, keep_results=False).start()
+    replay(server, trace)
+    server.drain(timeout=600)
+    st = server.stats()
+    scans = st["by_kind"][SCAN]["count"]
+    out = {
+        "workload": f"8 resident datasets (D {'/'.join(str(d) for d in synth.CFG5_DIMS)}, "
+                    f"4 b/dim, 1M stored records each); Poisson {rate:g} req/s for "
+                    f"{a.serve_seconds:g} s, 80 % encodes of log-uniform 1..131072 vectors, "
+                    "20 % 64-query estimate scans over 1M records; HBM budget 64 GiB",
+        "requests": st["requests"], "rejected": st["rejected"], "batches": st["batches"],
+        "encode": st["by_kind"][ENCODE], "scan": st["by_kind"][SCAN],
+        "encoded_vectors_per_s": st["vectors_per_s"],
+        "scanned_query_record_pairs_per_s": scans * n_store * 64 / a.serve_seconds,
+        "max_inflight_bytes": st["max_inflight_bytes"],
+        "max_queue": st["max_queue"],
+    }
+    del be, pools, queries
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(plan, X, a):

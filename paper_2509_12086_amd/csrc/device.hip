@@ -9,7 +9,8 @@
 //                    Algorithm 1 with FP64 decisions, the factor and the
 //                    bit-plane record.  One lane per vector, 64 vectors per
 //                    wave, all lanes on the same segment in lock step.
-//   estimate_kernel  Section 3.2 estimator over packed records.
+//   estimate_kernel  Section 3.2 estimator over packed records, as an FP32
+//                    matrix-core contraction of scaled codes with queries.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -610,70 +611,160 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 }
 
 // ---------------------------------------------------------------------------
-// Estimate scan: one thread per stored record, QG queries per block.  For
-// each kept segment the projected queries' slice is staged in LDS; the
-// record's bit planes are decoded 8 dims at a time into u = code - (2^B-1)/2
-// and dotted with every staged query; the segment sum is scaled by f_s.
+// Estimate scan (Section 3.2) as a matrix-core contraction:
+//   dist2[q][i] = ||o_i||^2 + ||q - c||^2 - 2 sum_s f_s <u_s(i), q'_s>
+// is a GEMM between the records' scaled codes a_i = (f_s u_s), one row of
+// D_kept values per record, and the projected queries q'.  A workgroup takes
+// 128 records x 64 queries; a k-step covers 32 kept dims of one segment.
+// Each k-step's raw inputs (16 dims of every bit plane for one record per
+// thread pair, 8 query values per thread, the record's f_s) are fetched one
+// k-step ahead and unpacked into LDS as FP32 f_s (c - (2^B - 1)/2) after the
+// MFMAs of the current k-step; the four waves then run 2 x 16
+// v_mfma_f32_32x32x2_f32 each (wave w: records 32w .. 32w + 31 against all
+// 64 queries).  A segment whose width is not a multiple of 32 pads its last
+// k-step with zeros on both operands.
 // ---------------------------------------------------------------------------
-constexpr int QG = 16;
+constexpr int ER = 128;                 // records per estimate tile
+constexpr int EQ = 64;                  // queries per estimate tile
+constexpr int EK = 32;                  // kept dims per k-step
+constexpr int ESTR = EK + 4;            // floats per LDS row (conflict-free b128 reads)
+constexpr int EST_LDS_FLOATS = 2 * (ER + EQ) * ESTR;   // 55,296 bytes
 
 __global__ __launch_bounds__(256) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n,
-    float* __restrict__ out, int max_w) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    float* qs = reinterpret_cast<float*>(smem);     // [QG][max_w]
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int q0 = blockIdx.y * QG;
-    const int nqg = min(QG, nq - q0);
-    const bool live = i < n;
-    const int64_t ii = live ? i : n - 1;
-    const uint8_t* rec = codes + ii * code_bytes;
-    const float* f = factors + ii * (n_kept + 1);
-    float acc[QG];
-#pragma unroll
-    for (int q = 0; q < QG; ++q) acc[q] = 0.f;
-    for (int s = 0; s < n_kept; ++s) {
-        const SegEntry e = segs[s];
+    float* __restrict__ out) {
+    __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
+    float (*As)[ER * ESTR] = reinterpret_cast<float (*)[ER * ESTR]>(lds);
+    float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds + 2 * ER * ESTR);
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63, li = lane & 31, lh = lane >> 5;
+    const int64_t r0 = int64_t(blockIdx.x) * ER;
+    const int q0 = blockIdx.y * EQ;
+
+    // unpacking: record ur of the tile, dims 16 uh .. 16 uh + 15 of a k-step;
+    // records past n read record n - 1 and are never stored
+    const int ur = t >> 1, uh = t & 1;
+    const int64_t ri = min(r0 + ur, n - 1);
+    const uint8_t* rec = codes + ri * code_bytes;
+    const float* fr = factors + ri * (n_kept + 1);
+    // query staging: query qq of the tile, dims qd .. qd + 7 of a k-step
+    const int qq = t >> 2, qd = (t & 3) * 8;
+    const bool qlive = q0 + qq < nq;
+    const float* qrow = Qp + int64_t(qlive ? q0 + qq : 0) * dk;
+
+    struct Raw { uint32_t w[16]; float q[8]; float fs; };
+    auto fetch = [&](Raw& g, int si, int j0) {
+        const SegEntry e = segs[si];
         const int W = e.width, B = e.bits, pb = (W + 7) >> 3;
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < QG * W; idx += blockDim.x) {
-            const int q = idx / W, j = idx - q * W;
-            qs[q * max_w + j] = q < nqg ? Qp[int64_t(q0 + q) * dk + e.col + j] : 0.f;
+        const int d0 = j0 + 16 * uh;
+        const bool any = d0 < W, two = d0 + 8 < W;
+        const uint8_t* pl = rec + e.code_off + (d0 >> 3);
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            uint32_t w = 0u;
+            if (p < B && any) {
+                w = pl[int64_t(p) * pb];
+                if (two) w |= uint32_t(pl[int64_t(p) * pb + 1]) << 8;
+            }
+            g.w[p] = w;
         }
-        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            const int j = j0 + qd + d;
+            g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
+        }
+        g.fs = fr[si];
+    };
+    auto put = [&](const Raw& g, int si, int j0, int buf) {
+        const SegEntry e = segs[si];
+        const int W = e.width, B = e.bits;
+        const int d0 = j0 + 16 * uh;
+        uint32_t c[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) c[d] = 0u;
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            if (p >= B) break;
+#pragma unroll
+            for (int d = 0; d < 16; ++d) c[d] = (c[d] << 1) | ((g.w[p] >> d) & 1u);
+        }
+        // f_s (c - h) with h = (2^B - 1)/2; c - h is exact in FP32
         const float h = 0.5f * float((1 << B) - 1);
-        float sacc[QG];
+        float a[16];
 #pragma unroll
-        for (int q = 0; q < QG; ++q) sacc[q] = 0.f;
-        for (int j = 0; j < pb; ++j) {
-            int c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            for (int p = 0; p < B; ++p) {
-                const unsigned byte = rec[e.code_off + int64_t(p) * pb + j];
+        for (int d = 0; d < 16; ++d) a[d] = (d0 + d < W) ? g.fs * (float(c[d]) - h) : 0.f;
+        float* ad = &As[buf][ur * ESTR + 16 * uh];
 #pragma unroll
-                for (int t2 = 0; t2 < 8; ++t2) c[t2] = (c[t2] << 1) | int((byte >> t2) & 1u);
+        for (int q = 0; q < 4; ++q)
+            *reinterpret_cast<float4*>(ad + 4 * q) = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+        float* bd = &Bs[buf][qq * ESTR + qd];
+        *reinterpret_cast<float4*>(bd) = make_float4(g.q[0], g.q[1], g.q[2], g.q[3]);
+        *reinterpret_cast<float4*>(bd + 4) = make_float4(g.q[4], g.q[5], g.q[6], g.q[7]);
+    };
+
+    floatx16 acc[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
+
+    // the k-steps in order: (segment s, first dim j0)
+    int s = 0, j0 = 0;
+    while (s < n_kept && segs[s].width <= 0) ++s;
+    if (s < n_kept) {
+        Raw g;
+        fetch(g, s, j0);
+        put(g, s, j0, 0);
+        __syncthreads();
+        for (int kt = 0;; ++kt) {
+            const int buf = kt & 1;
+            // the next k-step
+            int s1 = s, j1 = j0 + EK;
+            if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
+            const bool more = s1 < n_kept;
+            if (more) fetch(g, s1, j1);
+            const float* a0 = &As[buf][(32 * wave + li) * ESTR + lh * 16];
+            const float* b0 = &Bs[buf][li * ESTR + lh * 16];
+            const float* b1 = b0 + 32 * ESTR;
+            float A[16], B0[16], B1[16];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float4 va = *reinterpret_cast<const float4*>(a0 + 4 * q);
+                const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
+                const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
+                A[4 * q] = va.x; A[4 * q + 1] = va.y; A[4 * q + 2] = va.z; A[4 * q + 3] = va.w;
+                B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
+                B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
             }
-            float u[8];
 #pragma unroll
-            for (int t2 = 0; t2 < 8; ++t2) u[t2] = (8 * j + t2 < W) ? float(c[t2]) - h : 0.f;
-#pragma unroll
-            for (int q = 0; q < QG; ++q) {
-                const float* qq = qs + q * max_w + 8 * j;
-                float a = sacc[q];
-#pragma unroll
-                for (int t2 = 0; t2 < 8; ++t2)
-                    if (8 * j + t2 < W) a = fmaf(u[t2], qq[t2], a);
-                sacc[q] = a;
+            for (int j = 0; j < 16; ++j) {
+                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B0[j], acc[0], 0, 0, 0);
+                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B1[j], acc[1], 0, 0, 0);
             }
+            if (!more) break;
+            put(g, s1, j1, buf ^ 1);
+            __syncthreads();
+            s = s1;
+            j0 = j1;
         }
-        const float fs = f[s];
-#pragma unroll
-        for (int q = 0; q < QG; ++q) acc[q] = fmaf(fs, sacc[q], acc[q]);
     }
-    if (!live) return;
-    const float on = f[n_kept];
-    for (int q = 0; q < nqg; ++q) out[int64_t(q0 + q) * n + i] = on + qn2[q0 + q] - 2.f * acc[q];
+
+    // lane: query q0 + 32 bj + li; for register r the record
+    // r0 + 32 wave + 8 (r/4) + 4 lh + r%4
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int q = q0 + 32 * bj + li;
+        if (q >= nq) continue;
+        const float qn = qn2[q];
+        float* orow = out + int64_t(q) * n;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = r0 + 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
+            if (i < n) orow[i] = factors[i * (n_kept + 1) + n_kept] + qn - 2.f * acc[bj][r];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -971,14 +1062,9 @@ saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, cons
     float* qn2 = Qp + int64_t(nq) * std::max(p->D_kept, 1);
     saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st);
     if (s != SAQ_OK) return s;
-    const int maxw = std::max(p->max_kept_w, 1);
-    if (size_t(QG) * maxw * 4 > kMaxDynLds)
-        return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the estimate kernel's "
-                                           "LDS query buffer (1024 dims)");
-    const dim3 grid(unsigned((n + 255) / 256), unsigned((nq + QG - 1) / QG));
-    hipLaunchKernelGGL(estimate_kernel, grid, dim3(256), size_t(QG) * maxw * 4, st, Qp, nq,
-                       std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
-                       factors, n, out, maxw);
+    const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
+    hipLaunchKernelGGL(estimate_kernel, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1), qn2,
+                       dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }

@@ -195,8 +195,10 @@ class Server:
     """Continuous-batching encode/scan server over a backend."""
 
     def __init__(self, backend, hbm_budget: int, max_batch_vectors: int = 262144,
-                 clock: Callable[[], float] = time.monotonic, poll_s: float = 2e-4):
+                 clock: Callable[[], float] = time.monotonic, poll_s: float = 2e-4,
+                 keep_results: bool = True):
         self.be = backend
+        self.keep_results = keep_results      # False: record timings, drop results
         self.budget = int(hbm_budget)
         self.max_batch = int(max_batch_vectors)
         self.clock = clock
@@ -294,7 +296,7 @@ class Server:
                     del self.inflight[slot]
                     self.used -= nbytes
                     for r, res in results:
-                        r.result = res
+                        r.result = res if self.keep_results else None
                         r.finished = now
                         self.done.append(r)
                         r._event.set()
@@ -371,7 +373,18 @@ class Server:
             "vectors_per_s": vec / span if span > 0 else None,
             "max_queue": self.max_queue,
             "max_inflight_bytes": self.max_used,
+            "by_kind": {k: _percentiles([r.latency for r in self.done
+                                         if r.kind == k and r.error is None])
+                        for k in (ENCODE, SCAN)},
         }
+
+
+def _percentiles(lat) -> dict:
+    a = np.asarray(lat, dtype=np.float64)
+    if a.size == 0:
+        return {"count": 0}
+    return {"count": int(a.size), "p50_ms": float(np.percentile(a, 50) * 1e3),
+            "p99_ms": float(np.percentile(a, 99) * 1e3), "mean_ms": float(a.mean() * 1e3)}
 
 
 def replay(server: Server, trace: Sequence[Tuple[float, str, np.ndarray, str]],

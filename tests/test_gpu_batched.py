@@ -118,3 +118,29 @@ def test_autotuner_picks_a_valid_shape(batch):
                          "two grouped launches instead")
 def test_persistent_single_launch_pipeline():
     raise AssertionError("removed code path")
+
+
+def test_cfg3_full_size_batched_sampled():
+    """Four 1M x 3072 datasets (variance (i+1)^-1.2, budgets 1/2/4/8 b/dim,
+    6-12 segments of widths 16-512 and 1-9 bits) through saq_encode_batched
+    in the autotuned launch shape the benchmark times; 400 sampled records of
+    each dataset compared with the oracle."""
+    n = 1_000_000
+    entries = []
+    for i, b in enumerate((1.0, 2.0, 4.0, 8.0)):
+        ds = synth.cfg3(i, n)
+        say(f"cfg3 dataset {i}: generating {n} x 3072 on the device")
+        entries.append((_basis_plan(ds, b, granularity=16, max_bits=9, max_width=512),
+                        ds.rows_torch(n, cuda())))
+    best, _ = autotune.tune(entries, rounds=4, reps=1)
+    say(f"cfg3 batched encode, tuning {best}")
+    outs = saq.encode_batched(entries, 4, best)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(5).choice(n, 400, replace=False))
+    ti = torch.from_numpy(idx).to(cuda())
+    for (p, X), (c, f) in zip(entries, outs):
+        Xs = X[ti].cpu().numpy()
+        compare(p, c[ti].cpu().numpy(), f[ti].cpu().numpy(), oracle_encode(p, Xs, 4),
+                label=f"cfg3 D3072 {p.code_bytes * 8 // 3072} b/dim")
+    del entries, outs
+    torch.cuda.empty_cache()

@@ -196,6 +196,41 @@ def test_estimate_dist(cfg1):
     assert abs(e_gpu - e_orc) <= 0.01 * e_orc
 
 
+def test_estimate_dist_shapes():
+    """The estimate scan's tiles (128 records x 64 queries x 32 dims) on ragged
+    shapes: query counts around 64, record counts around 128, segment widths
+    that are not multiples of 32 (down to 3) and 1- to 16-bit segments; the
+    result equals the oracle's estimator on the same records (FP32
+    accumulation tolerance)."""
+    rng = np.random.default_rng(7)
+    lam = np.exp(-np.arange(99) / 20.0)
+    X = ((rng.standard_normal((1500, 99)) * np.sqrt(lam)) @ synth.haar_rotation(99, 4).T
+         ).astype(np.float32)
+    p99 = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=2.5, granularity=8, max_width=32,
+                                         fit_sample=0)).upload(0)
+    D = 160
+    Mw = np.eye(D, dtype=np.float32)[:128]
+    pw = saq.Plan.from_parts([16, 48, 32, 16, 16, 32], [16, 9, 5, 2, 1, 0], Mw,
+                             np.zeros(D, np.float32)).upload(0)
+    Xw = (rng.standard_normal((700, D)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3, 0.1],
+                                                     [16, 48, 32, 16, 16, 32])).astype(np.float32)
+    for plan, Xs in ((p99, X), (pw, Xw)):
+        for n, nq in ((1, 1), (127, 63), (129, 65), (len(Xs), 130)):
+            say(f"estimate D={plan.D} n={n} nq={nq}")
+            Q = (rng.standard_normal((nq, plan.D)) * Xs.std(0)).astype(np.float32)
+            packed, fac = gpu_encode(plan, Xs[:n], 4)
+            d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac))
+            torch.cuda.synchronize()
+            d2 = d2.cpu().numpy()
+            M, c, _ = plan.arrays()
+            codes = saq.unpack_codes(plan, packed)
+            ref = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
+                                  fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
+            scale = fac[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
+            assert d2.shape == (nq, n)
+            assert np.max(np.abs(d2 - ref) / scale) < 2e-5
+
+
 def test_device_argument_errors(cfg1):
     ds, X, plan = cfg1
     x = to_dev(X[:10])
