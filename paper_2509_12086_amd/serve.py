@@ -183,10 +183,12 @@ class _GpuBatch:
         return self.event.query()
 
     def finish(self):
+        # results are views of the batch's pinned host buffers (each view
+        # keeps its buffer alive); no host-side copy in the scheduler thread
         self.event.synchronize()
         out = []
         for r, hosts, sl in self.parts:
-            out.append((r, tuple(h.numpy()[sl].copy() for h in hosts)))
+            out.append((r, tuple(h.numpy()[sl] for h in hosts)))
         self.keep = None
         return out
 
