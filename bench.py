@@ -85,6 +85,8 @@ def parse():
                     help="length of the served-ingestion trace (0 = skip)")
     ap.add_argument("--batched-n", type=int, default=1_000_000,
                     help="vectors per dataset in the batched leg (0 = skip)")
+    ap.add_argument("--scan-only", action="store_true",
+                    help="only the estimate-scan leg (short runs under a profiler)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched leg (short runs under a profiler)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -110,6 +112,9 @@ def main():
     torch.cuda.set_device(dev)
     if a.batched_only:
         print(json.dumps({"batched": batched_leg(a)}), flush=True)
+        return
+    if a.scan_only:
+        print(json.dumps({"estimate_scan": scan_leg(a)}), flush=True)
         return
     ds = synth.cfg2(a.n)
     t0 = time.time()
@@ -189,9 +194,11 @@ def main():
         cpu = cpu_baseline(plan, X, a)
     del X, O, ws, codes, fac
     torch.cuda.empty_cache()
-    batched = None
+    batched = scans = None
     if a.batched_n > 0 and not a.kernels_only:
         batched = batched_leg(a)
+    if not a.kernels_only:
+        scans = scan_leg(a)
     serving = serving_mix = None
     if a.serve_seconds > 0 and not a.kernels_only:
         serving = serve_leg(a)
@@ -252,6 +259,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "batched": batched,
+        "estimate_scan": scans,
         "serving": serving,
         "serving_mix": serving_mix,
     }
@@ -432,6 +440,49 @@ def serve_leg(a):
         "plain_encoder_vectors_per_s": plain,
         "max_queue": st["max_queue"],
     }
+
+
+def scan_leg(a):
+    """Estimate scans (Section 3.2): 64 queries against 1M stored records
+    encoded at 4 b/dim, for D = 128, 768, 1536 and 3072 (variance
+    exp(-8i/D)); the scan kernel is an FP32 matrix-core contraction of the
+    records' scaled codes with the projected queries."""
+    import torch
+    import synth
+    import paper_2509_12086_amd as saq
+    dev = torch.device("cuda", 0)
+    n, nq = 1_000_000, 64
+    stream = torch.cuda.current_stream(dev)
+    rows = []
+    for i in (0, 2, 4, 6):
+        ds = synth.cfg5(i, n)
+        plan = saq.Plan.from_basis(np.zeros(ds.d), ds.rotation, ds.lam,
+                                   saq.PlanParams(bits_per_dim=4.0)).upload(0)
+        X = ds.rows_torch(n, dev)
+        codes, fac = saq.encode(plan, X, a.rounds)
+        del X
+        Q = ds.rows_torch(nq, dev, seed_offset=2)
+        out = torch.empty((nq, n), dtype=torch.float32, device=dev)
+        ws = torch.empty(plan.estimate_workspace_bytes(nq), dtype=torch.uint8, device=dev)
+        for _ in range(2):
+            saq.estimate_dist(plan, Q, codes, fac, out, ws, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        k = 5
+        for _ in range(k):
+            saq.estimate_dist(plan, Q, codes, fac, out, ws, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        flops = 2.0 * nq * plan.D_kept * n
+        rows.append({"D": ds.d, "D_kept": plan.D_kept, "code_bytes": plan.code_bytes,
+                     "ms_per_scan": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                     "frac_fp32_mfma": flops / (ms * 1e-3) / PEAK_FP32_MFMA,
+                     "record_GBps": n * (plan.code_bytes + 4 * plan.n_factors) / (ms * 1e-3) / 1e9})
+        del codes, fac, out, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{nq} queries x {n} records, 4 b/dim, D in 128/768/1536/3072", "scans": rows}
 
 
 def serve_mix_leg(a):

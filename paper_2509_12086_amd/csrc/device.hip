@@ -684,11 +684,14 @@ __global__ __launch_bounds__(256) void estimate_kernel(
         uint32_t c[16];
 #pragma unroll
         for (int d = 0; d < 16; ++d) c[d] = 0u;
+        // fully unrolled with a uniform predicate per plane, so g stays in
+        // registers (a loop exit would index it dynamically)
 #pragma unroll
         for (int p = 0; p < 16; ++p) {
-            if (p >= B) break;
+            if (p < B) {
 #pragma unroll
-            for (int d = 0; d < 16; ++d) c[d] = (c[d] << 1) | ((g.w[p] >> d) & 1u);
+                for (int d = 0; d < 16; ++d) c[d] = (c[d] << 1) | ((g.w[p] >> d) & 1u);
+            }
         }
         // f_s (c - h) with h = (2^B - 1)/2; c - h is exact in FP32
         const float h = 0.5f * float((1 << B) - 1);
