@@ -622,7 +622,9 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 // MFMAs of the current k-step; the four waves then run 2 x 16
 // v_mfma_f32_32x32x2_f32 each (wave w: records 32w .. 32w + 31 against all
 // 64 queries).  A segment whose width is not a multiple of 32 pads its last
-// k-step with zeros on both operands.
+// k-step with zeros on both operands.  Segments of at most 8 bits unpack a
+// plane byte (8 dims) with one lookup in a 256-entry table that spreads its
+// bits to one bit per byte.
 // ---------------------------------------------------------------------------
 constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
@@ -636,9 +638,17 @@ __global__ __launch_bounds__(256) void estimate_kernel(
     int64_t code_bytes, const float* __restrict__ factors, int64_t n,
     float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
+    __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
     float (*As)[ER * ESTR] = reinterpret_cast<float (*)[ER * ESTR]>(lds);
     float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds + 2 * ER * ESTR);
     const int t = threadIdx.x;
+    {
+        uint64_t v = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v |= uint64_t((t >> i) & 1) << (8 * i);
+        spread[t] = v;                    // blockDim.x == 256
+    }
+    __syncthreads();
     const int wave = t >> 6, lane = t & 63, li = lane & 31, lh = lane >> 5;
     const int64_t r0 = int64_t(blockIdx.x) * ER;
     const int q0 = blockIdx.y * EQ;
@@ -682,15 +692,34 @@ __global__ __launch_bounds__(256) void estimate_kernel(
         const int W = e.width, B = e.bits;
         const int d0 = j0 + 16 * uh;
         uint32_t c[16];
+        // loops fully unrolled with a uniform predicate per plane, so g stays
+        // in registers (a loop exit would index it dynamically)
+        if (B <= 8) {
+            // codes as the bytes of two words: each plane byte is spread to
+            // one bit per byte by the table and shifted in (a code below
+            // 2^8 never carries into the next byte)
+            uint64_t lo = 0, hi = 0;
 #pragma unroll
-        for (int d = 0; d < 16; ++d) c[d] = 0u;
-        // fully unrolled with a uniform predicate per plane, so g stays in
-        // registers (a loop exit would index it dynamically)
+            for (int p = 0; p < 8; ++p) {
+                if (p < B) {
+                    lo = (lo << 1) | spread[g.w[p] & 0xffu];
+                    hi = (hi << 1) | spread[(g.w[p] >> 8) & 0xffu];
+                }
+            }
 #pragma unroll
-        for (int p = 0; p < 16; ++p) {
-            if (p < B) {
+            for (int d = 0; d < 8; ++d) {
+                c[d] = uint32_t(lo >> (8 * d)) & 0xffu;
+                c[8 + d] = uint32_t(hi >> (8 * d)) & 0xffu;
+            }
+        } else {
 #pragma unroll
-                for (int d = 0; d < 16; ++d) c[d] = (c[d] << 1) | ((g.w[p] >> d) & 1u);
+            for (int d = 0; d < 16; ++d) c[d] = 0u;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) {
+                if (p < B) {
+#pragma unroll
+                    for (int d = 0; d < 16; ++d) c[d] = (c[d] << 1) | ((g.w[p] >> d) & 1u);
+                }
             }
         }
         // f_s (c - h) with h = (2^B - 1)/2; c - h is exact in FP32
