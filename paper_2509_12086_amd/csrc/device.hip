@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void project_kernel(
 // A round that accepts nothing leaves the state unchanged, so once no lane
 // of the wave accepted anything the remaining rounds are skipped.
 // ---------------------------------------------------------------------------
-constexpr int QCH = 16;   // dims per prefetch chunk in the quantize kernel
+constexpr int QCH = 32;   // dims per prefetch chunk in the quantize kernel
 
 // Where one lane's projected values sit.  Tiled layout: the 64 vectors of a
 // wave are one tile, dim j of the tile 64 contiguous floats, so a chunk is

@@ -515,18 +515,23 @@ saq_status saq_fit_plan(const float* X, int64_t n, int32_t D, const saq_plan_par
         const int64_t m = (p->fit_sample > 0 && p->fit_sample < n) ? p->fit_sample : n;
         std::vector<int64_t> rows(static_cast<size_t>(m));
         for (int64_t i = 0; i < m; ++i) rows[size_t(i)] = (m == n) ? i : (i * n) / m;
-        // mean
+        // mean: partial sums over fixed blocks of rows, added in block order,
+        // so the result does not depend on the thread count or schedule
         std::vector<double> mu(D, 0.0);
-#pragma omp parallel
         {
-            std::vector<double> part(D, 0.0);
-#pragma omp for schedule(static)
-            for (int64_t i = 0; i < m; ++i) {
-                const float* x = X + rows[size_t(i)] * D;
-                for (int k = 0; k < D; ++k) part[k] += double(x[k]);
+            const int64_t MB = 4096;
+            const int64_t nb = (m + MB - 1) / MB;
+            std::vector<double> part(size_t(nb) * D, 0.0);
+#pragma omp parallel for schedule(static)
+            for (int64_t b = 0; b < nb; ++b) {
+                double* pb = &part[size_t(b) * D];
+                for (int64_t i = b * MB; i < std::min(m, (b + 1) * MB); ++i) {
+                    const float* x = X + rows[size_t(i)] * D;
+                    for (int k = 0; k < D; ++k) pb[k] += double(x[k]);
+                }
             }
-#pragma omp critical
-            for (int k = 0; k < D; ++k) mu[k] += part[k];
+            for (int64_t b = 0; b < nb; ++b)
+                for (int k = 0; k < D; ++k) mu[k] += part[size_t(b) * D + k];
         }
         for (int k = 0; k < D; ++k) mu[k] /= double(m);
         // covariance (1/m) sum (x - c)(x - c)^T, blocked over rows; each block

@@ -117,27 +117,30 @@ class Dataset:
     def rows_torch(self, n: int, device, seed_offset: int = 0):
         """n rows generated on a torch device (for full-size GPU runs): the
         same distribution and structure (rotation, centers, spectrum) as
-        ``rows``, drawn from a seeded torch generator on that device.  Only
-        reproducible on the same device type and torch version; callers that
-        need the values on the host copy them back from the returned tensor."""
+        ``rows``, drawn from a seeded torch generator on that device.  The
+        scaling, centers and rotation are applied in FP64 and rounded to FP32
+        once, so the rows do not depend on which library GEMM kernel runs
+        (only on the device type and torch version, through the normal
+        draws).  Callers that need the values on the host copy them back from
+        the returned tensor."""
         import torch
         g = torch.Generator(device=device)
         g.manual_seed(self.seed * 1_000_003 + seed_offset)
-        R = torch.from_numpy(self.rotation.astype(np.float32)).to(device)
+        R = torch.from_numpy(self.rotation.astype(np.float64)).to(device)
         out = torch.empty((n, self.d), dtype=torch.float32, device=device)
         step = 65536
         if self.kind == "clusters":
-            C = torch.from_numpy(self.centers.astype(np.float32)).to(device)
-            sd = torch.from_numpy(self.std.astype(np.float32)).to(device)
+            C = torch.from_numpy(self.centers.astype(np.float64)).to(device)
+            sd = torch.from_numpy(self.std.astype(np.float64)).to(device)
         else:
-            sd = torch.from_numpy(np.sqrt(self.lam).astype(np.float32)).to(device)
+            sd = torch.from_numpy(np.sqrt(self.lam).astype(np.float64)).to(device)
         for a in range(0, n, step):
             b = min(n, a + step)
-            z = torch.randn((b - a, self.d), generator=g, device=device) * sd
+            z = torch.randn((b - a, self.d), generator=g, device=device).double() * sd
             if self.kind == "clusters":
                 ids = torch.randint(0, self.n_centers, (b - a,), generator=g, device=device)
                 z = z + C[ids]
-            out[a:b] = z @ R.T
+            out[a:b] = (z @ R.T).float()
         return out
 
     def queries(self, nq: int) -> np.ndarray:

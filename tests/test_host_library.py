@@ -164,3 +164,28 @@ def test_projection_accumulation_mode():
     for acc, want in ((0, 0), (1, 0), (2, 1)):
         p = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=2.0, fit_sample=0, projection_accumulation=acc))
         assert p.info["projection_fp64_totals"] == want
+
+
+def test_fit_is_independent_of_thread_count(tmp_path):
+    """The host fit gives bit-identical plans for any OpenMP thread count (its
+    reductions run over fixed row blocks in a fixed order)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, numpy as np; sys.path.insert(0, %r)\n"
+        "import synth, paper_2509_12086_amd as saq\n"
+        "X = synth.cfg1(9000).rows()\n"
+        "saq.Plan.fit(X, saq.PlanParams(bits_per_dim=4.0, fit_sample=0)).save(sys.argv[1])\n"
+    ) % root
+    paths = []
+    for threads in (1, 5):
+        out = str(tmp_path / f"plan_{threads}.saq")
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        subprocess.run([sys.executable, "-c", code, out], env=env, check=True, timeout=300)
+        paths.append(out)
+    a, b = (saq.Plan.load(p_) for p_ in paths)
+    for x, y in zip(a.arrays(), b.arrays()):
+        assert np.array_equal(x, y)
+    assert a.widths == b.widths and a.bits == b.bits
