@@ -28,7 +28,6 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int TM = saq::kGemmTileM;   // 128 vectors per tile
 constexpr int TN = saq::kGemmTileN;   // 128 kept dims per tile
 constexpr int TK = saq::kGemmTileK;   // 32 input dims per k-step
 constexpr int LDS_STRIDE = TK + 4;    // floats per LDS row (conflict-free b128 reads)
@@ -47,59 +46,75 @@ enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1, LAYOUT_TILES = 2 };
 // tiles x, x+8, ... and, inside each, all column tiles back to back, so the
 // X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
 // ---------------------------------------------------------------------------
-constexpr int GEMM_LDS_FLOATS = 2 * (TM + TN) * LDS_STRIDE;   // 73,728 bytes
+// BI = 32-row MFMA blocks per wave along the vectors: the workgroup tile is
+// (64 BI) vectors x 128 kept dims.  BI = 2 (FP32 accumulation): 128 x 128,
+// 73.7 KB of LDS, two workgroups per compute unit.  BI = 1 (FP64 k-tile
+// totals, which hold 64 doubles per 32 x 32 block and lane pair): 64 x 128,
+// 55.3 KB, so the totals fit two workgroups per compute unit as well.
+template <int BI> constexpr int gemm_rows() { return 64 * BI; }
+template <int BI> constexpr int gemm_lds_floats() { return 2 * (64 * BI + TN) * LDS_STRIDE; }
 
-// One 128 x 128 output tile (tile_m, tile_n).  lds: GEMM_LDS_FLOATS floats,
-// free on entry and on return (the last k-step ends with a barrier).
-template <int LAYOUT, bool ACC64, bool NORM>
+// One (64 BI) x 128 output tile (tile_m, tile_n).  lds: gemm_lds_floats<BI>()
+// floats, free on entry and on return (the last k-step ends with a barrier).
+template <int LAYOUT, bool ACC64, bool NORM, int BI>
 __device__ __forceinline__ void gemm_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
     float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
-    float (*As)[TM * LDS_STRIDE] = reinterpret_cast<float (*)[TM * LDS_STRIDE]>(lds);
-    float (*Bs)[TN * LDS_STRIDE] = reinterpret_cast<float (*)[TN * LDS_STRIDE]>(lds + 2 * TM * LDS_STRIDE);
-    const int64_t m0 = int64_t(tile_m) * TM;
+    static_assert(BI == 1 || BI == 2, "tile shapes: 64 x 128 or 128 x 128");
+    constexpr int RM = gemm_rows<BI>();          // vectors per tile
+    constexpr int ATPR = 256 / RM;               // threads per A row (4 or 2)
+    constexpr int ALK = TK / ATPR;               // A floats per thread per k-step
+    float (*As)[RM * LDS_STRIDE] = reinterpret_cast<float (*)[RM * LDS_STRIDE]>(lds);
+    float (*Bs)[TN * LDS_STRIDE] = reinterpret_cast<float (*)[TN * LDS_STRIDE]>(lds + 2 * RM * LDS_STRIDE);
+    const int64_t m0 = int64_t(tile_m) * RM;
     const int n0 = tile_n * TN;
 
     const int t = threadIdx.x;
-    const int lr = t >> 1;              // row loaded by this thread (A and B)
-    const int lk = (t & 1) * 16;        // k offset inside the tile
+    const int lr = t / ATPR;            // A row loaded by this thread
+    const int lk = (t % ATPR) * ALK;    // its k offset inside the tile
+    const int br = t >> 1;              // B row loaded by this thread
+    const int bk = (t & 1) * 16;
     const int64_t arow = m0 + lr;
     const bool arow_ok = arow < n;
     // rows past n read row n-1 (always valid memory) and are zeroed on store
     const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
-    const float* brow = Mp + int64_t(n0 + lr) * k_pad;
+    const float* brow = Mp + int64_t(n0 + br) * k_pad;
     double nacc = 0.0;
 
     // raw global values of the next tile; consumed only after the MFMAs of
     // the current tile so the loads overlap the matrix work
-    float rx[16], rc[16], rb[16];
+    float rx[ALK], rc[ALK], rb[16];
     auto load_full = [&](int k0) {          // k0 + 32 <= D (and VEC)
         const int kb = k0 + lk;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < ALK / 4; ++q) {
             const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
             const float4 c4 = *reinterpret_cast<const float4*>(cp + kb + 4 * q);
-            const float4 b4 = *reinterpret_cast<const float4*>(brow + kb + 4 * q);
             rx[4 * q + 0] = x4.x; rx[4 * q + 1] = x4.y; rx[4 * q + 2] = x4.z; rx[4 * q + 3] = x4.w;
             rc[4 * q + 0] = c4.x; rc[4 * q + 1] = c4.y; rc[4 * q + 2] = c4.z; rc[4 * q + 3] = c4.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 b4 = *reinterpret_cast<const float4*>(brow + k0 + bk + 4 * q);
             rb[4 * q + 0] = b4.x; rb[4 * q + 1] = b4.y; rb[4 * q + 2] = b4.z; rb[4 * q + 3] = b4.w;
         }
     };
     auto load_guarded = [&](int k0) {       // any tile: element loads below D
         const int kb = k0 + lk;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < ALK; ++e) {
             rx[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
             rc[e] = cp[kb + e];
-            rb[e] = brow[kb + e];
         }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) rb[e] = brow[k0 + bk + e];
     };
     // rows past n hold row n-1: their outputs and norms are never stored
     auto store_tile = [&](int buf) {
-        float ra[16];
+        float ra[ALK];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < ALK; ++e) {
             ra[e] = rx[e] - rc[e];
             if (NORM) {
                 // exact (x - c)^2 in FP64; padding entries are 0 - 0
@@ -108,12 +123,13 @@ __device__ __forceinline__ void gemm_tile_impl(
             }
         }
         float* a = &As[buf][lr * LDS_STRIDE + lk];
-        float* b = &Bs[buf][lr * LDS_STRIDE + lk];
+        float* b = &Bs[buf][br * LDS_STRIDE + bk];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < ALK / 4; ++q)
             *reinterpret_cast<float4*>(a + 4 * q) = make_float4(ra[4 * q], ra[4 * q + 1], ra[4 * q + 2], ra[4 * q + 3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
             *reinterpret_cast<float4*>(b + 4 * q) = make_float4(rb[4 * q], rb[4 * q + 1], rb[4 * q + 2], rb[4 * q + 3]);
-        }
     };
     // full tiles use 16-byte loads when the rows allow it
     const int kfull = vec ? (D / TK) : 0;
@@ -128,10 +144,10 @@ __device__ __forceinline__ void gemm_tile_impl(
     // zero and then added into FP64 totals, so the FP32 rounding error grows
     // with the tile length (32) rather than with D.  Otherwise the MFMAs
     // accumulate the whole dot product in FP32.
-    floatx16 acc[2][2];
-    double tot[2][2][ACC64 ? 16 : 1];
+    floatx16 acc[BI][2];
+    double tot[BI][2][ACC64 ? 16 : 1];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < BI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
 #pragma unroll
@@ -148,32 +164,33 @@ __device__ __forceinline__ void gemm_tile_impl(
         const int buf = kt & 1;
         const bool more = kt + 1 < ktiles;
         if (more) load_tile(kt + 1);
-        const float* a0 = &As[buf][(wm * 64 + li) * LDS_STRIDE + lh * 16];
-        const float* a1 = a0 + 32 * LDS_STRIDE;
+        const float* a0 = &As[buf][(wm * (32 * BI) + li) * LDS_STRIDE + lh * 16];
         const float* b0 = &Bs[buf][(wn * 64 + li) * LDS_STRIDE + lh * 16];
         const float* b1 = b0 + 32 * LDS_STRIDE;
-        float A0[16], A1[16], B0[16], B1[16];
+        float A[BI][16], B0[16], B1[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const float4 va0 = *reinterpret_cast<const float4*>(a0 + 4 * q);
-            const float4 va1 = *reinterpret_cast<const float4*>(a1 + 4 * q);
+#pragma unroll
+            for (int i = 0; i < BI; ++i) {
+                const float4 va = *reinterpret_cast<const float4*>(a0 + i * 32 * LDS_STRIDE + 4 * q);
+                A[i][4 * q] = va.x; A[i][4 * q + 1] = va.y; A[i][4 * q + 2] = va.z; A[i][4 * q + 3] = va.w;
+            }
             const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
             const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
-            A0[4 * q] = va0.x; A0[4 * q + 1] = va0.y; A0[4 * q + 2] = va0.z; A0[4 * q + 3] = va0.w;
-            A1[4 * q] = va1.x; A1[4 * q + 1] = va1.y; A1[4 * q + 2] = va1.z; A1[4 * q + 3] = va1.w;
             B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
             B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
         }
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B0[j], acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[j], B1[j], acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B0[j], acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[j], B1[j], acc[1][1], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < BI; ++i) {
+                acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B0[j], acc[i][0], 0, 0, 0);
+                acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B1[j], acc[i][1], 0, 0, 0);
+            }
         }
         if (ACC64) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < BI; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -187,21 +204,23 @@ __device__ __forceinline__ void gemm_tile_impl(
     }
 
     if (NORM) {
-        nacc += __shfl_xor(nacc, 1);
-        if ((t & 1) == 0 && arow_ok) norm2[arow] = float(nacc);
+        // the ATPR threads of a row are adjacent lanes
+        if (ATPR >= 2) nacc += __shfl_xor(nacc, 1);
+        if (ATPR >= 4) nacc += __shfl_xor(nacc, 2);
+        if ((t % ATPR) == 0 && arow_ok) norm2[arow] = float(nacc);
     }
 
     // epilogue: lane holds column n0 + wn*64 + 32*bj + li and, for register
-    // r, row m0 + wm*64 + 32*bi + 8*(r/4) + 4*lh + r%4
+    // r, row m0 + wm*32*BI + 32*bi + 8*(r/4) + 4*lh + r%4
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+    for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             const int col = n0 + wn * 64 + bj * 32 + li;
             if (col >= dk) continue;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const int64_t row = m0 + wm * 64 + bi * 32 + 8 * g + 4 * lh;
+                const int64_t row = m0 + wm * (32 * BI) + bi * 32 + 8 * g + 4 * lh;
                 float v0, v1, v2, v3;
                 if (ACC64) {
                     v0 = float(tot[bi][bj][(4 * g + 0) & (ACC64 ? 15 : 0)]);
@@ -241,31 +260,36 @@ __device__ __forceinline__ void gemm_tile_impl(
 
 // ||x - c||^2 is produced by the first column tile only; the k-loop is
 // specialised so the other tiles carry none of its work.
-template <int LAYOUT, bool ACC64>
+template <int LAYOUT, bool ACC64, int BI>
 __device__ __forceinline__ void gemm_tile(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
     float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
     if (norm2 != nullptr && tile_n == 0)
-        gemm_tile_impl<LAYOUT, ACC64, true>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
-                                            tile_n, lds);
+        gemm_tile_impl<LAYOUT, ACC64, true, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
+                                                tile_m, tile_n, lds);
     else
-        gemm_tile_impl<LAYOUT, ACC64, false>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
-                                             tile_n, lds);
+        gemm_tile_impl<LAYOUT, ACC64, false, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
+                                                 tile_m, tile_n, lds);
 }
+
+// FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
+template <bool ACC64> constexpr int gemm_bi() { return ACC64 ? 1 : 2; }
 
 template <bool VEC, int LAYOUT, bool ACC64>
 __global__ __launch_bounds__(256) void project_kernel(
     const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
     const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
     float* __restrict__ norm2, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(16))) float lds[GEMM_LDS_FLOATS];
+    constexpr int BI = gemm_bi<ACC64>();
+    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_floats<BI>()];
     const int bid = blockIdx.x;
     const int xcd = bid % NXCD, local = bid / NXCD;
     const int tile_n = local % tiles_n;
     const int tile_m = (local / tiles_n) * NXCD + xcd;
     if (tile_m >= tiles_m) return;
-    gemm_tile<LAYOUT, ACC64>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n, lds);
+    gemm_tile<LAYOUT, ACC64, BI>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n,
+                                 lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -559,7 +583,8 @@ struct GemmArgs { GemmSet set[BATCH_MAX]; int count; int xcd_order; };
 
 template <bool ACC64>
 __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) {
-    __shared__ __attribute__((aligned(16))) float lds[GEMM_LDS_FLOATS];
+    constexpr int BI = gemm_bi<ACC64>();
+    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_floats<BI>()];
     const int64_t b = blockIdx.x;
     int d = 0;
     while (d + 1 < args.count && b >= args.set[d + 1].first_block) ++d;
@@ -578,12 +603,14 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) 
         tile_n = int(lb % S.tiles_n);
     }
     if (tile_m >= S.tiles_m) return;
+    // one tile shape per launch: in a launch with FP64 totals, datasets
+    // without them accumulate in FP32 on the same tile
     if (S.acc64)
-        gemm_tile<LAYOUT_TILES, ACC64>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
-                                      S.ld, S.norm2, tile_m, tile_n, lds);
+        gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
+                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds);
     else
-        gemm_tile<LAYOUT_TILES, false>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk, S.O,
-                                      S.ld, S.norm2, tile_m, tile_n, lds);
+        gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
+                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds);
 }
 
 struct QuantSet {
@@ -822,7 +849,8 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O, int64_t ld,
                           int layout, float* norm2, hipStream_t st) {
-    const int tiles_m = int((n + TM - 1) / TM);
+    const int rows = p->acc64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
+    const int tiles_m = int((n + rows - 1) / rows);
     const int tiles_n = p->layout.n_pad / TN;
     const int slots = (tiles_m + NXCD - 1) / NXCD;
     const dim3 grid(unsigned(NXCD * slots * tiles_n));
@@ -891,6 +919,7 @@ struct BatchPlan {
     int64_t gemm_blocks = 0, quant_blocks = 0, ws_need = 0;
     int waves = 1;
     bool wide = false;
+    bool any64 = false;       // some dataset takes FP64 k-tile totals
     size_t lds = 0;
 };
 
@@ -904,6 +933,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         return saq::fail(SAQ_EINVAL, "batch must hold 1..16 datasets");
     if (rounds < 0) return saq::fail(SAQ_EINVAL, "rounds < 0");
     int wmax = 1;
+    B.any64 = false;
     for (int i = 0; i < count; ++i) {
         const saq_batch_item& it = items[i];
         if (!uploaded(it.plan)) return saq::fail(SAQ_EINVAL, "batch plan not uploaded");
@@ -913,6 +943,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         if (it.n > 0) {
             wmax = std::max(wmax, it.plan->max_kept_w);
             B.wide |= it.plan->max_kept_b > 8;
+            B.any64 |= it.plan->acc64;
         }
     }
     const size_t cs = B.wide ? 2 : 1;
@@ -944,7 +975,8 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
         G.vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
         G.Mp = dev_M(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
-        G.tiles_m = int((it.n + TM - 1) / TM); G.tiles_n = p->layout.n_pad / TN;
+        const int rows = B.any64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
+        G.tiles_m = int((it.n + rows - 1) / rows); G.tiles_n = p->layout.n_pad / TN;
         G.O = O; G.ld = ld; G.norm2 = nrm;
         G.first_block = B.gemm_blocks;
         B.gemm_blocks += xcd ? int64_t(NXCD) * ((G.tiles_m + NXCD - 1) / NXCD) * G.tiles_n
@@ -1056,8 +1088,7 @@ saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_
     if (ws_bytes < B.ws_need) return saq::fail(SAQ_EINVAL, "workspace too small");
     if (B.g.count == 0) return SAQ_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    bool any64 = false;
-    for (int i = 0; i < B.g.count; ++i) any64 |= B.g.set[i].acc64 != 0;
+    const bool any64 = B.any64;
     // one instantiation handles both kinds of datasets; the FP32-only one
     // keeps the register budget of two workgroups per compute unit
     if (any64)
