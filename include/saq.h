@@ -134,7 +134,9 @@ saq_status saq_plan_upload(saq_plan* plan, void* dev_buf, void* stream);
    adjustment of Algorithm 1 (stopping early once a round changes nothing,
    which cannot alter the result), then the stored factors and the bit-plane
    record.  codes_dev [n x code_bytes], factors_dev [n x n_factors].
-   ws_dev: saq_encode_workspace_bytes(plan, n) bytes of device scratch. */
+   ws_dev: saq_encode_workspace_bytes(plan, n) bytes of device scratch.
+   A kept segment wider than the quantize kernel's LDS code buffer (1024 dims
+   at <= 8 bits, 512 dims above) gives SAQ_EUNSUPPORTED. */
 int64_t    saq_encode_workspace_bytes(const saq_plan* plan, int64_t n);
 saq_status saq_encode(const saq_plan* plan, const float* X_dev, int64_t n, int32_t rounds,
                       uint8_t* codes_dev, float* factors_dev, void* ws_dev, int64_t ws_bytes,

@@ -947,6 +947,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         }
     }
     const size_t cs = B.wide ? 2 : 1;
+    if (tuning && tuning->reserved != 0) return saq::fail(SAQ_EINVAL, "saq_batch_tuning.reserved must be 0");
     const int want = tuning && tuning->quant_waves > 0 ? tuning->quant_waves : 1;
     if (want != 1 && want != 2 && want != 4) return saq::fail(SAQ_EINVAL, "quant_waves must be 1, 2 or 4");
     if (size_t(wmax) * 64 * cs > kMaxDynLds)

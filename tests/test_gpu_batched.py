@@ -97,6 +97,13 @@ def test_batched_argument_errors(batch):
         saq.encode_batched([(p, X)], 4, workspace=small)
     with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
         saq.encode_batched([(p, X)], -2)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p, X)], 4, saq.BatchTuning(quant_waves=3))
+    # the reserved field of saq_batch_tuning must be 0
+    import ctypes
+    arr = saq._batch_struct([(p, X, None, None)])
+    t = saq._Tuning(1, 1, 7)
+    assert saq.lib().saq_encode_batched_workspace_bytes(arr, 1, ctypes.byref(t)) == -1
 
 
 def test_autotuner_picks_a_valid_shape(batch):
