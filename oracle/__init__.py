@@ -60,7 +60,7 @@ def lib():
         L.saqo_encode.argtypes = [P, i64, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P, P,
                                   ctypes.c_int]
         L.saqo_pack.argtypes = [P, i64, i32, i32, P, P, P, i64]
-        L.saqo_estimate.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64, P,
+        L.saqo_estimate.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64, i32, P,
                                     ctypes.c_int]
         for f in ("saqo_quantize", "saqo_project", "saqo_encode", "saqo_pack", "saqo_estimate"):
             getattr(L, f).restype = ctypes.c_int
@@ -150,8 +150,11 @@ def pack(codes: np.ndarray, widths: Sequence[int], bits: Sequence[int]) -> np.nd
 
 
 def estimate(Q: np.ndarray, M: np.ndarray, c: np.ndarray, widths, bits, codes: np.ndarray,
-             factors: np.ndarray, norm2: np.ndarray, threads: int = 0) -> np.ndarray:
-    """Estimated squared distances [nq, n] (Section 3.2)."""
+             factors: np.ndarray, norm2: np.ndarray, threads: int = 0,
+             prefix_bits: int = 0) -> np.ndarray:
+    """Estimated squared distances [nq, n] (Section 3.2); prefix_bits > 0
+    uses the progressive approximation from the first min(prefix_bits, B)
+    bits of every code."""
     Q = np.ascontiguousarray(Q, np.float32)
     M = np.ascontiguousarray(M, np.float32)
     c = np.ascontiguousarray(c, np.float32)
@@ -162,7 +165,8 @@ def estimate(Q: np.ndarray, M: np.ndarray, c: np.ndarray, widths, bits, codes: n
     nq, n = Q.shape[0], codes.shape[0]
     out = np.zeros((nq, n), np.float64)
     if lib().saqo_estimate(_p(Q), nq, Q.shape[1], _p(M), M.shape[0], _p(c), w.size, _p(w),
-                           _p(b), _p(codes), _p(factors), _p(norm2), n, _p(out), threads):
+                           _p(b), _p(codes), _p(factors), _p(norm2), n, int(prefix_bits),
+                           _p(out), threads):
         raise ValueError("oracle estimate: bad arguments")
     return out
 

@@ -16,7 +16,8 @@
  *   stored factors      end of Section 3.1 (norm and <o_a, o>)
  *   segments            Section 4.1-4.2: each segment of the plan is
  *                       quantized on its own "just as a normal vector"
- *   estimator           Section 3.2, Eq. (estimator_inner_product)
+ *   estimator           Section 3.2, Eq. (estimator_inner_product), and its
+ *                       progressive approximation from b-bit code prefixes
  *
  * Readings where the paper is silent (the same list is kept in the design
  * notes of the repository):
@@ -287,10 +288,17 @@ int saqo_pack(const int32_t *codes, int64_t n, int32_t Dk, int32_t nseg,
  * (dimensions of dropped segments contribute nothing to the inner product;
  * ||o||^2 = ||x - c||^2 is the stored full norm).
  */
+/* Estimator of Section 3.2, Eq. (estimator_inner_product), per segment:
+ * <o_s, q_s> ~= <o_a, q_s> / <o_a, o_s> * ||o_s||^2 with o_a = Delta u, i.e.
+ * f_s <u_s, q_s>.  prefix > 0 takes the progressive approximation of
+ * Section 3.2 with b = min(prefix, B) bits per dimension: the prefix code
+ * c_s = floor(c / 2^(B-b)) replaces c and Delta' = Delta 2^(B-b) replaces
+ * Delta in o_a, so o_a becomes Delta' u' with u' = c_s - (2^b - 1)/2 while
+ * the stored <o_a, o_s> is kept: the term is f_s 2^(B-b) <u'_s, q_s>. */
 int saqo_estimate(const float *Q, int32_t nq, int32_t D, const float *M, int32_t Dk,
                   const float *c, int32_t nseg, const int32_t *seg_w, const int32_t *seg_b,
                   const int32_t *codes, const double *factors, const double *norm2,
-                  int64_t n, double *d2, int nthreads)
+                  int64_t n, int32_t prefix, double *d2, int nthreads)
 {
     double *qp = (double *)malloc(sizeof(double) * (size_t)(nq * Dk > 0 ? nq * Dk : 1));
     double *qn = (double *)malloc(sizeof(double) * (size_t)(nq > 0 ? nq : 1));
@@ -302,11 +310,16 @@ int saqo_estimate(const float *Q, int32_t nq, int32_t D, const float *M, int32_t
             double ip = 0.0;
             int off = 0;
             for (int s = 0; s < nseg; ++s) {
-                const double h = (ldexp(1.0, seg_b[s]) - 1.0) / 2.0;
+                const int B = seg_b[s];
+                const int b = (prefix > 0 && prefix < B) ? prefix : B;
+                const int shift = B - b;
+                const double h = (ldexp(1.0, b) - 1.0) / 2.0;
                 double uq = 0.0;
-                for (int i = 0; i < seg_w[s]; ++i)
-                    uq += ((double)codes[r * Dk + off + i] - h) * qp[(int64_t)qi * Dk + off + i];
-                ip += factors[r * nseg + s] * uq;
+                for (int i = 0; i < seg_w[s]; ++i) {
+                    const int cs = (int)floor((double)codes[r * Dk + off + i] / ldexp(1.0, shift));
+                    uq += ((double)cs - h) * qp[(int64_t)qi * Dk + off + i];
+                }
+                ip += factors[r * nseg + s] * ldexp(1.0, shift) * uq;
                 off += seg_w[s];
             }
             d2[(int64_t)qi * n + r] = norm2[r] + qn[qi] - 2.0 * ip;
