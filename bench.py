@@ -476,10 +476,24 @@ def scan_leg(a):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / k
         flops = 2.0 * nq * plan.D_kept * n
-        rows.append({"D": ds.d, "D_kept": plan.D_kept, "code_bytes": plan.code_bytes,
-                     "ms_per_scan": ms, "tflops": flops / (ms * 1e-3) / 1e12,
-                     "frac_fp32_mfma": flops / (ms * 1e-3) / PEAK_FP32_MFMA,
-                     "record_GBps": n * (plan.code_bytes + 4 * plan.n_factors) / (ms * 1e-3) / 1e9})
+        row = {"D": ds.d, "D_kept": plan.D_kept, "code_bytes": plan.code_bytes,
+               "ms_per_scan": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+               "frac_fp32_mfma": flops / (ms * 1e-3) / PEAK_FP32_MFMA,
+               "record_GBps": n * (plan.code_bytes + 4 * plan.n_factors) / (ms * 1e-3) / 1e9}
+        if ds.d == 3072:
+            # progressive approximation: only the first b bit planes are read
+            pre = {}
+            for b in (1, 2, 4):
+                saq.estimate_dist(plan, Q, codes, fac, out, ws, stream, prefix_bits=b)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(k):
+                    saq.estimate_dist(plan, Q, codes, fac, out, ws, stream, prefix_bits=b)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                pre[str(b)] = e0.elapsed_time(e1) / k
+            row["prefix_ms_per_scan"] = pre
+        rows.append(row)
         del codes, fac, out, ws
     torch.cuda.empty_cache()
     return {"workload": f"{nq} queries x {n} records, 4 b/dim, D in 128/768/1536/3072", "scans": rows}

@@ -182,6 +182,20 @@ saq_status saq_estimate_dist(const saq_plan* plan, const float* Q_dev, int32_t n
                              const uint8_t* codes_dev, const float* factors_dev, int64_t n,
                              float* dist2_dev, void* ws_dev, int64_t ws_bytes, void* stream);
 
+/* The same estimate from code prefixes (progressive approximation, Section
+   3.2): every kept segment with B bits reads only its first
+   b = min(prefix_bits, B) bit planes, i.e. the prefix codes
+   c_s = floor(c / 2^(B-b)), which stand for the B-bit grid with
+   Delta' = Delta 2^(B-b):
+     dist2_dev[q * n + i] = ||o_i||^2 + ||q - c||^2
+                            - 2 sum_s f_s 2^(B-b) <c_s - (2^b - 1)/2, q'_s>.
+   prefix_bits = 0 (or >= every B) is saq_estimate_dist; < 0 gives
+   SAQ_EINVAL.  Same workspace as saq_estimate_dist. */
+saq_status saq_estimate_dist_prefix(const saq_plan* plan, const float* Q_dev, int32_t nq,
+                                    const uint8_t* codes_dev, const float* factors_dev,
+                                    int64_t n, int32_t prefix_bits, float* dist2_dev,
+                                    void* ws_dev, int64_t ws_bytes, void* stream);
+
 /* Batched encode: many datasets, each with its own uploaded plan (uneven
    segment widths and bits), in two grouped launches for the whole batch --
    one for every dataset's projection tiles, one for every dataset's

@@ -55,7 +55,8 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_plan_info_get", "saq_plan_segments", "saq_plan_arrays", "saq_plan_save",
            "saq_plan_load", "saq_plan_free", "saq_plan_device_bytes", "saq_plan_upload",
            "saq_encode_workspace_bytes", "saq_encode", "saq_project", "saq_quantize",
-           "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_encode_batched_workspace_bytes",
+           "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_estimate_dist_prefix",
+           "saq_encode_batched_workspace_bytes",
            "saq_encode_batched", "saq_last_error", "saq_version")
 
 BATCH_MAX = 16
@@ -101,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "saq_quantize": (i32, [P, P, i64, i32, i64, P, i32, P, P, P]),
         "saq_estimate_workspace_bytes": (i64, [P, i32]),
         "saq_estimate_dist": (i32, [P, P, i32, P, P, i64, P, P, i64, P]),
+        "saq_estimate_dist_prefix": (i32, [P, P, i32, P, P, i64, i32, P, P, i64, P]),
         "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
         "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
         "saq_last_error": (ctypes.c_char_p, []),
@@ -361,8 +363,11 @@ def quantize(plan: Plan, O, rounds: int = 4, norm2=None, codes=None, factors=Non
     return codes, factors
 
 
-def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, stream=None):
-    """saq_estimate_dist: estimated squared distances f32 [nq, n]."""
+def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, stream=None,
+                  prefix_bits: int = 0):
+    """saq_estimate_dist: estimated squared distances f32 [nq, n]; with
+    prefix_bits > 0, saq_estimate_dist_prefix (each segment's first
+    min(prefix_bits, B) bits only)."""
     torch = _torch()
     _require_cuda_f32(Q, "Q", plan.D)
     nq, n = Q.shape[0], codes.shape[0]
@@ -371,10 +376,11 @@ def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, strea
     need = plan.estimate_workspace_bytes(nq)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=Q.device)
-    _check(lib().saq_estimate_dist(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes), _dev_ptr(factors), n,
-                                   _dev_ptr(out), _dev_ptr(workspace),
-                                   workspace.numel() * workspace.element_size(),
-                                   _stream_ptr(stream, Q.device)))
+    _check(lib().saq_estimate_dist_prefix(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes),
+                                          _dev_ptr(factors), n, int(prefix_bits), _dev_ptr(out),
+                                          _dev_ptr(workspace),
+                                          workspace.numel() * workspace.element_size(),
+                                          _stream_ptr(stream, Q.device)))
     return out
 
 

@@ -651,7 +651,9 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 // 64 queries).  A segment whose width is not a multiple of 32 pads its last
 // k-step with zeros on both operands.  Segments of at most 8 bits unpack a
 // plane byte (8 dims) with one lookup in a 256-entry table that spreads its
-// bits to one bit per byte.
+// bits to one bit per byte.  With prefix b > 0 a segment reads only its
+// first min(b, B) bit planes, the b-bit prefix floor(c / 2^(B-b)) of every
+// code, and scales its factor by 2^(B-b) (progressive approximation).
 // ---------------------------------------------------------------------------
 constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
@@ -662,7 +664,7 @@ constexpr int EST_LDS_FLOATS = 2 * (ER + EQ) * ESTR;   // 55,296 bytes
 __global__ __launch_bounds__(256) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
-    int64_t code_bytes, const float* __restrict__ factors, int64_t n,
+    int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
     float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
     __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
@@ -692,9 +694,12 @@ __global__ __launch_bounds__(256) void estimate_kernel(
     const float* qrow = Qp + int64_t(qlive ? q0 + qq : 0) * dk;
 
     struct Raw { uint32_t w[16]; float q[8]; float fs; };
+    // bits of a segment the scan reads: all of them, or the first `prefix`
+    // (progressive approximation, Section 3.2)
+    auto used_bits = [&](int B) { return (prefix > 0 && prefix < B) ? prefix : B; };
     auto fetch = [&](Raw& g, int si, int j0) {
         const SegEntry e = segs[si];
-        const int W = e.width, B = e.bits, pb = (W + 7) >> 3;
+        const int W = e.width, B = used_bits(e.bits), pb = (W + 7) >> 3;
         const int d0 = j0 + 16 * uh;
         const bool any = d0 < W, two = d0 + 8 < W;
         const uint8_t* pl = rec + e.code_off + (d0 >> 3);
@@ -712,11 +717,12 @@ __global__ __launch_bounds__(256) void estimate_kernel(
             const int j = j0 + qd + d;
             g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
         }
-        g.fs = fr[si];
+        // the b-bit prefix estimates with the stored factor times 2^(B - b)
+        g.fs = ldexpf(fr[si], e.bits - B);
     };
     auto put = [&](const Raw& g, int si, int j0, int buf) {
         const SegEntry e = segs[si];
-        const int W = e.width, B = e.bits;
+        const int W = e.width, B = used_bits(e.bits);
         const int d0 = j0 + 16 * uh;
         uint32_t c[16];
         // loops fully unrolled with a uniform predicate per plane, so g stays
@@ -1112,11 +1118,13 @@ int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     return int64_t(std::max(nq, 1)) * std::max(p->D_kept, 1) * 4 + int64_t(std::max(nq, 1)) * 4 + 512;
 }
 
-saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, const uint8_t* codes,
-                             const float* factors, int64_t n, float* out, void* ws,
-                             int64_t ws_bytes, void* stream) {
+saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t nq,
+                                    const uint8_t* codes, const float* factors, int64_t n,
+                                    int32_t prefix_bits, float* out, void* ws, int64_t ws_bytes,
+                                    void* stream) {
     if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
     if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (prefix_bits < 0) return saq::fail(SAQ_EINVAL, "prefix_bits < 0");
     if (nq == 0 || n == 0) return SAQ_OK;
     if (!Q || !codes || !factors || !out || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
     if (ws_bytes < saq_estimate_workspace_bytes(p, nq)) return saq::fail(SAQ_EINVAL, "workspace too small");
@@ -1128,9 +1136,16 @@ saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, cons
     if (s != SAQ_OK) return s;
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
     hipLaunchKernelGGL(estimate_kernel, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1), qn2,
-                       dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, out);
+                       dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
+                       out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
+}
+
+saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, const uint8_t* codes,
+                             const float* factors, int64_t n, float* out, void* ws,
+                             int64_t ws_bytes, void* stream) {
+    return saq_estimate_dist_prefix(p, Q, nq, codes, factors, n, 0, out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -231,6 +231,40 @@ def test_estimate_dist_shapes():
             assert np.max(np.abs(d2 - ref) / scale) < 2e-5
 
 
+def test_estimate_dist_prefix():
+    """Progressive estimation from code prefixes (Section 3.2): for several
+    prefix lengths the scan equals the oracle's prefix estimator on the same
+    records (FP32 accumulation tolerance), on a 4 b/dim plan and on 1- to
+    16-bit segments."""
+    rng = np.random.default_rng(8)
+    ds = synth.cfg1(3000)
+    X = ds.rows()
+    p1 = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=4.0, fit_sample=0)).upload(0)
+    D = 160
+    Mw = np.eye(D, dtype=np.float32)[:128]
+    pw = saq.Plan.from_parts([16, 48, 32, 16, 16, 32], [16, 9, 5, 2, 1, 0], Mw,
+                             np.zeros(D, np.float32)).upload(0)
+    Xw = (rng.standard_normal((700, D)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3, 0.1],
+                                                     [16, 48, 32, 16, 16, 32])).astype(np.float32)
+    for plan, Xs in ((p1, X), (pw, Xw)):
+        Q = (rng.standard_normal((70, plan.D)) * Xs.std(0)).astype(np.float32)
+        packed, fac = gpu_encode(plan, Xs, 4)
+        M, c, _ = plan.arrays()
+        codes = saq.unpack_codes(plan, packed)
+        scale = fac[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
+        for b in (1, 2, 3, 5, 8, 12):
+            say(f"estimate prefix D={plan.D} b={b}")
+            d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac), prefix_bits=b)
+            torch.cuda.synchronize()
+            ref = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
+                                  fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64),
+                                  prefix_bits=b)
+            assert np.max(np.abs(d2.cpu().numpy() - ref) / scale) < 2e-5, b
+    packed1, fac1 = gpu_encode(p1, X[:10], 4)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.estimate_dist(p1, to_dev(X[:4]), to_dev(packed1), to_dev(fac1), prefix_bits=-1)
+
+
 def test_device_argument_errors(cfg1):
     ds, X, plan = cfg1
     x = to_dev(X[:10])
