@@ -62,7 +62,10 @@ def lib():
         L.saqo_pack.argtypes = [P, i64, i32, i32, P, P, P, i64]
         L.saqo_estimate.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64, i32, P,
                                     ctypes.c_int]
-        for f in ("saqo_quantize", "saqo_project", "saqo_encode", "saqo_pack", "saqo_estimate"):
+        L.saqo_estimate_multistage.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64,
+                                               P, P, ctypes.c_double, P, P, P, P, ctypes.c_int]
+        for f in ("saqo_quantize", "saqo_project", "saqo_encode", "saqo_pack", "saqo_estimate",
+                  "saqo_estimate_multistage"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -169,6 +172,39 @@ def estimate(Q: np.ndarray, M: np.ndarray, c: np.ndarray, widths, bits, codes: n
                            _p(out), threads):
         raise ValueError("oracle estimate: bad arguments")
     return out
+
+
+def estimate_multistage(Q: np.ndarray, M: np.ndarray, c: np.ndarray, widths, bits,
+                        codes: np.ndarray, factors: np.ndarray, norm2: np.ndarray,
+                        P: np.ndarray, lam: np.ndarray, m: float, tau: np.ndarray,
+                        threads: int = 0):
+    """Multi-stage estimator of Section 4.3: returns (d2 [nq, n], stage [nq, n],
+    sigma [nq, k]).  A pair pruned before reading segment t has stage t and
+    d2 = the stage-t lower bound; stage k means the full estimate.  P [Dk, D]
+    are the kept PCA axes (unrotated, plan order) and lam [Dk] their
+    variances; sigma_s^2 = sum_{i in s} lam_i (P_i (q - c))^2."""
+    Q = np.ascontiguousarray(Q, np.float32)
+    M = np.ascontiguousarray(M, np.float32)
+    c = np.ascontiguousarray(c, np.float32)
+    codes = np.ascontiguousarray(codes, np.int32)
+    factors = np.ascontiguousarray(factors, np.float64)
+    norm2 = np.ascontiguousarray(norm2, np.float64)
+    P = np.ascontiguousarray(P, np.float64)
+    lam = np.ascontiguousarray(lam, np.float64)
+    tau = np.ascontiguousarray(np.broadcast_to(np.asarray(tau, np.float64), (Q.shape[0],)))
+    w, b = _kept(widths, bits)
+    nq, n = Q.shape[0], codes.shape[0]
+    if P.shape != (M.shape[0], Q.shape[1]) or lam.shape != (M.shape[0],):
+        raise ValueError("P must be [Dk, D] and lam [Dk]")
+    d2 = np.zeros((nq, n), np.float64)
+    stage = np.zeros((nq, n), np.int32)
+    sigma = np.zeros((nq, w.size), np.float64)
+    if lib().saqo_estimate_multistage(_p(Q), nq, Q.shape[1], _p(M), M.shape[0], _p(c), w.size,
+                                      _p(w), _p(b), _p(codes), _p(factors), _p(norm2), n,
+                                      _p(P), _p(lam), float(m), _p(tau), _p(d2), _p(stage),
+                                      _p(sigma), threads):
+        raise ValueError("oracle multi-stage estimate: bad arguments")
+    return d2, stage, sigma
 
 
 def true_dist2(Q: np.ndarray, X: np.ndarray) -> np.ndarray:

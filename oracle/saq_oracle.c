@@ -18,6 +18,8 @@
  *                       quantized on its own "just as a normal vector"
  *   estimator           Section 3.2, Eq. (estimator_inner_product), and its
  *                       progressive approximation from b-bit code prefixes
+ *   multi-stage         Section 4.3: segments read in plan order, the unread
+ *                       ones bounded by m sigma_Seg (Chebyshev)
  *
  * Readings where the paper is silent (the same list is kept in the design
  * notes of the repository):
@@ -325,6 +327,87 @@ int saqo_estimate(const float *Q, int32_t nq, int32_t D, const float *M, int32_t
             d2[(int64_t)qi * n + r] = norm2[r] + qn[qi] - 2.0 * ip;
         }
     free(qp); free(qn);
+    return 0;
+}
+
+/*
+ * Multi-stage estimator of Section 4.3.
+ *
+ * The kept segments are read in plan order, which is decreasing variance.
+ * Before segment t is read, the segments already read give their Section 3.2
+ * terms est_s = f_s <u_s, q'_s>.  The unread ones are bounded through
+ * Chebyshev's inequality: |<o_s, q_s>| < m sigma_s with probability at least
+ * 1 - 1/m^2, where
+ *   sigma_s^2 = sum_{i in s} q[i]^2 sigma_i^2
+ * is the variance over the data of the segment's inner product.  That sum
+ * needs uncorrelated dimensions, so q[i] is the query's coordinate on PCA
+ * axis i, P_i (q - c), and sigma_i^2 = lambda_i is that axis's variance.  The
+ * inner product does not change under the per-segment rotation, so sigma_s
+ * bounds the rotated segment as well.  The lower bound on the estimated
+ * squared distance at stage t is
+ *   LB_t = ||o||^2 + ||q - c||^2 - 2 (sum_{s<t} est_s + m sum_{s>=t} sigma_s).
+ * A pair (query, record) is pruned at the first t < k with LB_t > tau[q]; it
+ * then gets d2 = LB_t and stage = t (segments 0..t-1 were read).  A pair that
+ * is never pruned gets the full estimate and stage = k.
+ *
+ * P [Dk x D] holds the PCA axes of the kept dimensions in plan order (rows,
+ * unrotated) and lam [Dk] their variances.  sigma [nq x k] (optional) gets
+ * sigma_s per query.
+ */
+int saqo_estimate_multistage(const float *Q, int32_t nq, int32_t D, const float *M, int32_t Dk,
+                             const float *c, int32_t nseg, const int32_t *seg_w,
+                             const int32_t *seg_b, const int32_t *codes, const double *factors,
+                             const double *norm2, int64_t n, const double *P, const double *lam,
+                             double m, const double *tau, double *d2, int32_t *stage,
+                             double *sigma, int nthreads)
+{
+    if (nq < 0 || n < 0 || nseg < 0 || Dk < 0 || D <= 0 || !(m >= 0.0)) return 1;
+    const size_t nqs = (size_t)(nq > 0 ? nq : 1);
+    double *qp = (double *)malloc(sizeof(double) * nqs * (size_t)(Dk > 0 ? Dk : 1));
+    double *qn = (double *)malloc(sizeof(double) * nqs);
+    double *sg = (double *)malloc(sizeof(double) * nqs * (size_t)(nseg > 0 ? nseg : 1));
+    int rc = saqo_project(Q, nq, D, M, Dk, c, qp, qn, nthreads);
+    if (rc) { free(qp); free(qn); free(sg); return rc; }
+    /* sigma_s from the query's PCA coordinates */
+    for (int qi = 0; qi < nq; ++qi) {
+        int off = 0;
+        for (int s = 0; s < nseg; ++s) {
+            double v = 0.0;
+            for (int i = 0; i < seg_w[s]; ++i) {
+                double y = 0.0;
+                for (int k = 0; k < D; ++k)
+                    y += P[(int64_t)(off + i) * D + k] * ((double)Q[(int64_t)qi * D + k] - (double)c[k]);
+                v += lam[off + i] * y * y;
+            }
+            sg[(int64_t)qi * nseg + s] = sqrt(v);
+            if (sigma) sigma[(int64_t)qi * nseg + s] = sqrt(v);
+            off += seg_w[s];
+        }
+    }
+#pragma omp parallel for schedule(static) collapse(2)
+    for (int qi = 0; qi < nq; ++qi)
+        for (int64_t r = 0; r < n; ++r) {
+            const double *sq = sg + (int64_t)qi * nseg;
+            double ip = 0.0;
+            int t = 0, off = 0;
+            double out = 0.0;
+            for (; t < nseg; ++t) {
+                double rest = 0.0;                  /* sum of sigma_s over s >= t */
+                for (int s = t; s < nseg; ++s) rest += sq[s];
+                const double lb = norm2[r] + qn[qi] - 2.0 * (ip + m * rest);
+                if (lb > tau[qi]) { out = lb; break; }
+                const double h = (ldexp(1.0, seg_b[t]) - 1.0) / 2.0;
+                double uq = 0.0;
+                for (int i = 0; i < seg_w[t]; ++i)
+                    uq += ((double)codes[r * Dk + off + i] - h) * qp[(int64_t)qi * Dk + off + i];
+                ip += factors[r * nseg + t] * uq;
+                off += seg_w[t];
+            }
+            if (t == nseg) out = norm2[r] + qn[qi] - 2.0 * ip;
+            d2[(int64_t)qi * n + r] = out;
+            stage[(int64_t)qi * n + r] = t;
+        }
+    free(qp); free(qn); free(sg);
     return 0;
 }
 
