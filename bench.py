@@ -442,6 +442,55 @@ def serve_leg(a):
     }
 
 
+def multistage_timing(plan, Q, codes, fac, plain_out, ws, stream, k, m=4.0, sub=16384):
+    """Multi-stage scan (Section 4.3) at the paper's default m = 4.  Each
+    query's threshold is its 10th smallest estimate over the first 16,384
+    records (a pruning threshold a search would hold after a first probe).
+    Reports the time per scan, the code bits read per (query, record) pair,
+    the share of pairs closed early, and the share of the full scan's 10
+    nearest that stay open; then the same for a single query, where each
+    workgroup holds one query's pairs and can stop early."""
+    import torch
+    import paper_2509_12086_amd as saq
+    nq, n = plain_out.shape
+    dev = plain_out.device
+    part = torch.empty((nq, sub), dtype=torch.float32, device=dev)
+    saq.estimate_dist(plan, Q, codes[:sub], fac[:sub], part, ws, stream)
+    tau = torch.kthvalue(part, 10, dim=1).values.contiguous()
+    saq.estimate_dist(plan, Q, codes, fac, plain_out, ws, stream)
+    top = torch.topk(plain_out, 10, dim=1, largest=False).indices
+    out = torch.empty_like(plain_out)
+    stage = torch.empty((nq, n), dtype=torch.uint8, device=dev)
+    seg_bits = [w * b for w, b in zip(plan.kept_widths, plan.kept_bits)]
+    cum = torch.tensor(np.concatenate([[0], np.cumsum(seg_bits)]), dtype=torch.float64, device=dev)
+    kk = len(seg_bits)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms = timed(lambda: saq.estimate_multistage(plan, Q, codes, fac, tau, m, out, stage, ws, stream))
+    st = stage.long()
+    res = {"m": m, "ms_per_scan": ms,
+           "bits_per_pair": float(cum[st].mean()), "bits_full": int(sum(seg_bits)),
+           "closed_frac": float((st < kk).double().mean()),
+           "top10_open_frac": float((torch.gather(st, 1, top) == kk).double().mean())}
+    q1, t1, o1, s1 = Q[:1], tau[:1], out[:1], stage[:1]
+    res["nq1_plain_ms"] = timed(lambda: saq.estimate_dist(plan, q1, codes, fac, o1, ws, stream))
+    res["nq1_ms"] = timed(lambda: saq.estimate_multistage(plan, q1, codes, fac, t1, m, o1, s1, ws,
+                                                          stream))
+    res["nq1_bits_per_pair"] = float(cum[s1.long()].mean())
+    del part, out, stage, st
+    return res
+
+
 def scan_leg(a):
     """Estimate scans (Section 3.2): 64 queries against 1M stored records
     encoded at 4 b/dim, for D = 128, 768, 1536 and 3072 (variance
@@ -493,6 +542,7 @@ def scan_leg(a):
                 torch.cuda.synchronize()
                 pre[str(b)] = e0.elapsed_time(e1) / k
             row["prefix_ms_per_scan"] = pre
+        row["multistage"] = multistage_timing(plan, Q, codes, fac, out, ws, stream, k)
         rows.append(row)
         del codes, fac, out, ws
     torch.cuda.empty_cache()

@@ -106,7 +106,10 @@ saq_status saq_plan_from_basis(const double* mean, const double* eigvecs,
 
 /* A plan given explicitly: n_seg segments (widths summing to D, bits in
    0..16), M [D_kept x D] FP32 row-major whose rows follow the kept segments
-   in order, c [D] FP32, and optional per-dim variances [D] (may be NULL). */
+   in order, c [D] FP32, and optional per-dim variances [D] (may be NULL).
+   The variances are taken as those of M's rows, which are assumed
+   uncorrelated (the multi-stage bound of saq_estimate_multistage uses them;
+   without them it returns SAQ_EINVAL). */
 saq_status saq_plan_from_parts(int32_t D, int32_t n_seg, const int32_t* widths,
                                const int32_t* bits, const float* M, const float* c,
                                const double* variances, saq_plan** out);
@@ -195,6 +198,32 @@ saq_status saq_estimate_dist_prefix(const saq_plan* plan, const float* Q_dev, in
                                     const uint8_t* codes_dev, const float* factors_dev,
                                     int64_t n, int32_t prefix_bits, float* dist2_dev,
                                     void* ws_dev, int64_t ws_bytes, void* stream);
+
+/* Multi-stage estimate with Chebyshev pruning (Section 4.3).  The kept
+   segments are read in plan order (decreasing variance).  Before segment t,
+   the distance of a pair (query q, record i) is bounded from below by
+     LB_t = ||o_i||^2 + ||q - c||^2 - 2 (sum_{s<t} f_s <u_s, q'_s> + m sum_{s>=t} sigma_s),
+   with sigma_s^2 = sum_{j in s} lambda_j (P_j (q - c))^2 the variance over the
+   data of the segment's inner product (P_j the PCA axis behind kept dim j,
+   lambda_j its variance; the plan's per-segment rotation does not change
+   it), so each unread segment exceeds m sigma_s with probability at most
+   1/m^2.  The first t < k with LB_t > tau_dev[q] closes the pair:
+     dist2_dev[q * n + i] = LB_t,        stage_dev[q * n + i] = t;
+   a pair never closed gets the full Section 3.2 estimate and stage k (the
+   number of kept segments), so the bits read for it are
+   sum_{s < stage} B_s W_s.  tau_dev [nq] FP32 thresholds (e.g. the current
+   k-th best distance; +inf closes nothing and gives saq_estimate_dist's
+   values), m >= 0 (the paper's default is 4), stage_dev [nq x n] uint8 or
+   NULL.  A workgroup stops reading codes once every pair it holds is
+   closed.  Same workspace as saq_estimate_dist.
+   Errors: SAQ_EINVAL for a plan without variances (saq_plan_from_parts
+   without them), m < 0 or not finite; SAQ_EUNSUPPORTED for plans with more
+   than 255 kept segments, a kept segment wider than 4096 dims, or none. */
+saq_status saq_estimate_multistage(const saq_plan* plan, const float* Q_dev, int32_t nq,
+                                   const uint8_t* codes_dev, const float* factors_dev,
+                                   int64_t n, const float* tau_dev, float m, float* dist2_dev,
+                                   uint8_t* stage_dev, void* ws_dev, int64_t ws_bytes,
+                                   void* stream);
 
 /* Batched encode: many datasets, each with its own uploaded plan (uneven
    segment widths and bits), in two grouped launches for the whole batch --

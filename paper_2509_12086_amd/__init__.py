@@ -56,6 +56,7 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_plan_load", "saq_plan_free", "saq_plan_device_bytes", "saq_plan_upload",
            "saq_encode_workspace_bytes", "saq_encode", "saq_project", "saq_quantize",
            "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_estimate_dist_prefix",
+           "saq_estimate_multistage",
            "saq_encode_batched_workspace_bytes",
            "saq_encode_batched", "saq_last_error", "saq_version")
 
@@ -103,6 +104,8 @@ def lib() -> ctypes.CDLL:
         "saq_estimate_workspace_bytes": (i64, [P, i32]),
         "saq_estimate_dist": (i32, [P, P, i32, P, P, i64, P, P, i64, P]),
         "saq_estimate_dist_prefix": (i32, [P, P, i32, P, P, i64, i32, P, P, i64, P]),
+        "saq_estimate_multistage": (i32, [P, P, i32, P, P, i64, P, ctypes.c_float, P, P, P, i64,
+                                          P]),
         "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
         "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
         "saq_last_error": (ctypes.c_char_p, []),
@@ -363,25 +366,64 @@ def quantize(plan: Plan, O, rounds: int = 4, norm2=None, codes=None, factors=Non
     return codes, factors
 
 
+def _scan_buffers(plan: Plan, Q, codes, factors, out, workspace):
+    """Shape and type checks shared by the scans; allocates what is None."""
+    torch = _torch()
+    _require_cuda_f32(Q, "Q", plan.D)
+    nq, n = Q.shape[0], codes.shape[0]
+    for t, name in ((codes, "codes"), (factors, "factors")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.device == Q.device):
+            raise TypeError(f"{name} must be a CUDA tensor on Q's device")
+    _alloc_out(plan, n, Q.device, codes, factors)
+    if out is None:
+        out = torch.empty((nq, n), dtype=torch.float32, device=Q.device)
+    _require_cuda_f32(out, "out", n)
+    if out.shape[0] != nq:
+        raise ValueError("out must be [nq, n]")
+    need = plan.estimate_workspace_bytes(nq)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=Q.device)
+    elif workspace.numel() * workspace.element_size() < need:
+        raise ValueError(f"workspace needs {need} bytes")
+    return nq, n, out, workspace
+
+
 def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, stream=None,
                   prefix_bits: int = 0):
     """saq_estimate_dist: estimated squared distances f32 [nq, n]; with
     prefix_bits > 0, saq_estimate_dist_prefix (each segment's first
     min(prefix_bits, B) bits only)."""
-    torch = _torch()
-    _require_cuda_f32(Q, "Q", plan.D)
-    nq, n = Q.shape[0], codes.shape[0]
-    if out is None:
-        out = torch.empty((nq, n), dtype=torch.float32, device=Q.device)
-    need = plan.estimate_workspace_bytes(nq)
-    if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device=Q.device)
+    nq, n, out, workspace = _scan_buffers(plan, Q, codes, factors, out, workspace)
     _check(lib().saq_estimate_dist_prefix(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes),
                                           _dev_ptr(factors), n, int(prefix_bits), _dev_ptr(out),
                                           _dev_ptr(workspace),
                                           workspace.numel() * workspace.element_size(),
                                           _stream_ptr(stream, Q.device)))
     return out
+
+
+def estimate_multistage(plan: Plan, Q, codes, factors, tau, m: float = 4.0, out=None,
+                        stage=None, workspace=None, stream=None):
+    """saq_estimate_multistage (Section 4.3): returns (dist2 f32 [nq, n],
+    stage u8 [nq, n]).  tau: CUDA float32 [nq] thresholds; a pair whose lower
+    bound before segment t exceeds its query's threshold gets that bound and
+    stage t, the others the full estimate and stage k."""
+    torch = _torch()
+    nq, n, out, workspace = _scan_buffers(plan, Q, codes, factors, out, workspace)
+    _require_cuda_f32(tau, "tau", ndim=1)
+    if tau.shape[0] != nq:
+        raise ValueError("tau must have one threshold per query")
+    if stage is None:
+        stage = torch.empty((nq, n), dtype=torch.uint8, device=Q.device)
+    if stage.shape != (nq, n) or stage.dtype != torch.uint8 or not stage.is_contiguous() \
+            or not stage.is_cuda:
+        raise ValueError("stage must be a contiguous CUDA uint8 tensor [nq, n]")
+    _check(lib().saq_estimate_multistage(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes),
+                                         _dev_ptr(factors), n, _dev_ptr(tau), float(m),
+                                         _dev_ptr(out), _dev_ptr(stage), _dev_ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream_ptr(stream, Q.device)))
+    return out, stage
 
 
 def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:

@@ -56,7 +56,11 @@ template <int BI> constexpr int gemm_lds_floats() { return 2 * (64 * BI + TN) * 
 
 // One (64 BI) x 128 output tile (tile_m, tile_n).  lds: gemm_lds_floats<BI>()
 // floats, free on entry and on return (the last k-step ends with a barrier).
-template <int LAYOUT, bool ACC64, bool NORM, int BI>
+// FULLB: both of the wave's 32-column blocks hold kept dims.  Without it
+// (a wave of the last column tile whose second block lies past dk) the wave
+// runs only its first block's MFMAs; the waves of one workgroup may take
+// different variants, which share the same barrier sequence.
+template <int LAYOUT, bool ACC64, bool NORM, int BI, bool FULLB = true>
 __device__ __forceinline__ void gemm_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
@@ -185,7 +189,8 @@ __device__ __forceinline__ void gemm_tile_impl(
 #pragma unroll
             for (int i = 0; i < BI; ++i) {
                 acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B0[j], acc[i][0], 0, 0, 0);
-                acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B1[j], acc[i][1], 0, 0, 0);
+                if (FULLB)
+                    acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B1[j], acc[i][1], 0, 0, 0);
             }
         }
         if (ACC64) {
@@ -265,12 +270,18 @@ __device__ __forceinline__ void gemm_tile(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
     float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
+    // the wave's second 32-column block (wave w covers columns
+    // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
+    const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
     if (norm2 != nullptr && tile_n == 0)
         gemm_tile_impl<LAYOUT, ACC64, true, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
                                                 tile_m, tile_n, lds);
+    else if (fullb)
+        gemm_tile_impl<LAYOUT, ACC64, false, BI, true>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
+                                                       norm2, tile_m, tile_n, lds);
     else
-        gemm_tile_impl<LAYOUT, ACC64, false, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
-                                                 tile_m, tile_n, lds);
+        gemm_tile_impl<LAYOUT, ACC64, false, BI, false>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
+                                                        norm2, tile_m, tile_n, lds);
 }
 
 // FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
@@ -654,6 +665,15 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 // bits to one bit per byte.  With prefix b > 0 a segment reads only its
 // first min(b, B) bit planes, the b-bit prefix floor(c / 2^(B-b)) of every
 // code, and scales its factor by 2^(B-b) (progressive approximation).
+//
+// Multi-stage mode (MS, Section 4.3, prefix 0): the k-steps already run
+// segment by segment in plan order, so when a segment starts the
+// accumulators hold the terms of the segments before it.  There every lane
+// bounds its 32 (query, record) pairs from below,
+//   LB_s = ||o||^2 - 2 acc + lbq[q][s],  lbq[q][s] = ||q - c||^2 - 2 m sum_{t>=s} sigma_t,
+// and a pair with LB_s > tau[q] is closed: it gets LB_s and stage s.  Pairs
+// still open after the last segment get the full estimate and stage k.
+// Once no pair of the workgroup is open, the workgroup stops reading codes.
 // ---------------------------------------------------------------------------
 constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
@@ -661,10 +681,12 @@ constexpr int EK = 32;                  // kept dims per k-step
 constexpr int ESTR = EK + 4;            // floats per LDS row (conflict-free b128 reads)
 constexpr int EST_LDS_FLOATS = 2 * (ER + EQ) * ESTR;   // 55,296 bytes
 
+template <bool MS>
 __global__ __launch_bounds__(256) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
+    const float* __restrict__ lbq, const float* __restrict__ tau, uint8_t* __restrict__ stage,
     float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
     __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
@@ -775,16 +797,62 @@ __global__ __launch_bounds__(256) void estimate_kernel(
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[b][r] = 0.f;
 
+    // lane's pairs: query q0 + 32 bj + li, for register r the record
+    // r0 + 32 wave + 8 (r/4) + 4 lh + r%4; bit 16 bj + r of `open` is set
+    // while that pair is live and not pruned (multi-stage mode only)
+    auto rec_of = [&](int r) { return r0 + 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3); };
+    uint32_t open = 0;
+    float on2[16];
+    if constexpr (MS) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = rec_of(r);
+            on2[r] = i < n ? factors[i * (n_kept + 1) + n_kept] : 0.f;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+                if (i < n && q0 + 32 * bj + li < nq) open |= 1u << (16 * bj + r);
+        }
+    }
+    // close the pairs whose bound before segment si exceeds their threshold;
+    // true while any pair of the workgroup is still open
+    auto prune = [&](int si) -> bool {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int q = q0 + 32 * bj + li;
+            if (q >= nq) continue;
+            const float lb = lbq[int64_t(q) * n_kept + si], th = tau[q];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const uint32_t bit = 1u << (16 * bj + r);
+                if (open & bit) {
+                    const float v = (on2[r] - 2.f * acc[bj][r]) + lb;
+                    if (v > th) {
+                        open &= ~bit;
+                        const int64_t i = rec_of(r);
+                        out[int64_t(q) * n + i] = v;
+                        if (stage) stage[int64_t(q) * n + i] = uint8_t(si);
+                    }
+                }
+            }
+        }
+        return __syncthreads_or(open != 0u) != 0;
+    };
+
     // the k-steps in order: (segment s, first dim j0)
     int s = 0, j0 = 0;
     while (s < n_kept && segs[s].width <= 0) ++s;
-    if (s < n_kept) {
+    bool go = s < n_kept;
+    if constexpr (MS) go = go && prune(s);
+    if (go) {
         Raw g;
         fetch(g, s, j0);
         put(g, s, j0, 0);
         __syncthreads();
         for (int kt = 0;; ++kt) {
             const int buf = kt & 1;
+            if constexpr (MS) {
+                if (kt > 0 && j0 == 0 && !prune(s)) break;
+            }
             // the next k-step
             int s1 = s, j1 = j0 + EK;
             if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
@@ -826,9 +894,64 @@ __global__ __launch_bounds__(256) void estimate_kernel(
         float* orow = out + int64_t(q) * n;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            const int64_t i = r0 + 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3);
-            if (i < n) orow[i] = factors[i * (n_kept + 1) + n_kept] + qn - 2.f * acc[bj][r];
+            const int64_t i = rec_of(r);
+            if constexpr (MS) {
+                if (open & (1u << (16 * bj + r))) {
+                    orow[i] = on2[r] + qn - 2.f * acc[bj][r];
+                    if (stage) stage[int64_t(q) * n + i] = uint8_t(n_kept);
+                }
+            } else {
+                if (i < n) orow[i] = factors[i * (n_kept + 1) + n_kept] + qn - 2.f * acc[bj][r];
+            }
         }
+    }
+}
+
+// sigma_s of Section 4.3 for query blockIdx.y and kept segment blockIdx.x:
+// ||S_s q'_s||, the standard deviation over the data of <o_s, q_s>.  A wave
+// takes rows of the segment's block (coalesced along the row), the query
+// slice sits in LDS.
+constexpr int SIG_MAXW = 4096;
+__global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp, int dk,
+                                                    const SegEntry* __restrict__ segs, int n_kept,
+                                                    const float* __restrict__ S,
+                                                    float* __restrict__ sig) {
+    __shared__ float qs[SIG_MAXW];
+    __shared__ float part[4];
+    const int si = blockIdx.x, q = blockIdx.y;
+    int64_t off = 0;
+    for (int t = 0; t < si; ++t) off += int64_t(segs[t].width) * segs[t].width;
+    const SegEntry e = segs[si];
+    const int W = e.width;
+    const float* qrow = Qp + int64_t(q) * dk + e.col;
+    for (int j = threadIdx.x; j < W; j += 256) qs[j] = qrow[j];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float v = 0.f;
+    for (int i = wave; i < W; i += 4) {
+        const float* row = S + off + int64_t(i) * W;
+        float y = 0.f;
+        for (int j = lane; j < W; j += 64) y = fmaf(row[j], qs[j], y);
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) y += __shfl_xor(y, d);
+        v = fmaf(y, y, v);
+    }
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) sig[int64_t(q) * n_kept + si] = sqrtf((part[0] + part[1]) + (part[2] + part[3]));
+}
+
+// lbq[q][s] = ||q - c||^2 - 2 m sum_{t >= s} sigma_t, one thread per query
+__global__ __launch_bounds__(256) void stage_bound_kernel(const float* __restrict__ sig,
+                                                          const float* __restrict__ qn2, int nq,
+                                                          int n_kept, float m,
+                                                          float* __restrict__ lbq) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    float t = 0.f;
+    for (int si = n_kept - 1; si >= 0; --si) {
+        t += sig[int64_t(q) * n_kept + si];
+        lbq[int64_t(q) * n_kept + si] = qn2[q] - 2.f * m * t;
     }
 }
 
@@ -849,6 +972,9 @@ const float* dev_c(const saq_plan* p) {
 }
 const SegEntry* dev_seg(const saq_plan* p) {
     return reinterpret_cast<const SegEntry*>(static_cast<const char*>(p->dev) + p->layout.off_seg);
+}
+const float* dev_S(const saq_plan* p) {
+    return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_S);
 }
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -1115,7 +1241,9 @@ saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_
 
 int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     if (!p || nq < 0) return -1;
-    return int64_t(std::max(nq, 1)) * std::max(p->D_kept, 1) * 4 + int64_t(std::max(nq, 1)) * 4 + 512;
+    const int64_t q = std::max(nq, 1);
+    // Qp [nq x D_kept], ||q - c||^2 [nq], sigma and stage bounds [nq x n_kept] each
+    return q * std::max(p->D_kept, 1) * 4 + q * 4 + 2 * q * std::max(p->n_kept, 1) * 4 + 512;
 }
 
 saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t nq,
@@ -1135,10 +1263,53 @@ saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t n
     saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st);
     if (s != SAQ_OK) return s;
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
-    hipLaunchKernelGGL(estimate_kernel, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1), qn2,
-                       dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
-                       out);
+    hipLaunchKernelGGL(estimate_kernel<false>, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1),
+                       qn2, dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
+                       nullptr, nullptr, nullptr, out);
     const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
+}
+
+saq_status saq_estimate_multistage(const saq_plan* p, const float* Q, int32_t nq,
+                                   const uint8_t* codes, const float* factors, int64_t n,
+                                   const float* tau, float m, float* out, uint8_t* stage, void* ws,
+                                   int64_t ws_bytes, void* stream) {
+    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (!(m >= 0.f) || !std::isfinite(m)) return saq::fail(SAQ_EINVAL, "m must be finite and >= 0");
+    if (p->S.empty())
+        return saq::fail(SAQ_EINVAL, "plan has no variances: the multi-stage bound needs them");
+    if (p->n_kept > 255) return saq::fail(SAQ_EUNSUPPORTED, "multi-stage scan: more than 255 kept segments");
+    if (p->max_kept_w > SIG_MAXW)
+        return saq::fail(SAQ_EUNSUPPORTED, "multi-stage scan: a kept segment wider than 4096 dims");
+    if (nq == 0 || n == 0 || p->n_kept == 0) {
+        if (nq > 0 && n > 0 && p->n_kept == 0)
+            return saq::fail(SAQ_EUNSUPPORTED, "multi-stage scan: the plan keeps no segment");
+        return SAQ_OK;
+    }
+    if (!Q || !codes || !factors || !tau || !out || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
+    if (ws_bytes < saq_estimate_workspace_bytes(p, nq)) return saq::fail(SAQ_EINVAL, "workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    const int dk = std::max(p->D_kept, 1);
+    float* Qp = reinterpret_cast<float*>(base);
+    float* qn2 = Qp + int64_t(nq) * dk;
+    float* sig = qn2 + nq;
+    float* lbq = sig + int64_t(nq) * p->n_kept;
+    saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st);
+    if (s != SAQ_OK) return s;
+    hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq)), dim3(256), 0, st, Qp, dk,
+                       dev_seg(p), p->n_kept, dev_S(p), sig);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "sigma_kernel launch");
+    hipLaunchKernelGGL(stage_bound_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, sig, qn2,
+                       nq, p->n_kept, m, lbq);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "stage_bound_kernel launch");
+    const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
+    hipLaunchKernelGGL(estimate_kernel<true>, grid, dim3(256), 0, st, Qp, nq, dk, qn2, dev_seg(p),
+                       p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau, stage, out);
+    e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
 

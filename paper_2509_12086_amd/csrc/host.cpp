@@ -36,7 +36,8 @@ DeviceLayout device_layout(const saq_plan& p) {
     L.off_M = 0;
     L.off_c = align256(L.off_M + int64_t(L.n_pad) * L.k_pad * 4);
     L.off_seg = align256(L.off_c + int64_t(L.k_pad) * 4);
-    L.bytes = align256(L.off_seg + int64_t(std::max(p.n_kept, 1)) * int64_t(sizeof(SegEntry)));
+    L.off_S = align256(L.off_seg + int64_t(std::max(p.n_kept, 1)) * int64_t(sizeof(SegEntry)));
+    L.bytes = align256(L.off_S + int64_t(std::max<size_t>(p.S.size(), 1)) * 4);
     return L;
 }
 
@@ -50,6 +51,30 @@ void build_staging(saq_plan& p) {
     float* c = reinterpret_cast<float*>(p.staging.data() + L.off_c);
     std::memcpy(c, p.c.data(), size_t(p.D) * 4);
     std::memcpy(p.staging.data() + L.off_seg, p.kept.data(), p.kept.size() * sizeof(SegEntry));
+    if (!p.S.empty()) std::memcpy(p.staging.data() + L.off_S, p.S.data(), p.S.size() * 4);
+}
+
+// The blocks S_s for kept segments without a rotation: diag(sqrt(var)) of
+// the dims' own variances (empty if every variance is 0, i.e. unknown).
+static std::vector<float> diagonal_spread(const std::vector<int32_t>& widths,
+                                          const std::vector<int32_t>& bits,
+                                          const std::vector<double>& var) {
+    bool any = false;
+    for (double v : var) any = any || v != 0.0;
+    std::vector<float> S;
+    if (!any) return S;
+    int col = 0;
+    for (size_t s = 0; s < widths.size(); ++s) {
+        const int W = widths[s];
+        if (bits[s] > 0) {
+            const size_t base = S.size();
+            S.resize(base + size_t(W) * W, 0.0f);
+            for (int i = 0; i < W; ++i)
+                S[base + size_t(i) * W + i] = float(std::sqrt(std::max(var[size_t(col + i)], 0.0)));
+        }
+        col += W;
+    }
+    return S;
 }
 
 // ---------------------------------------------------------------------------
@@ -424,6 +449,15 @@ static saq_status make_plan(int32_t D, const std::vector<double>& mean, const st
         if (r.bits[s] > 0) {
             std::vector<double> R;
             if (P.rotate_segments) R = haar(W, P.seed * 0x100000001B3ull + uint64_t(s) + 1);
+            // spread block: S_s[i][j] = sqrt(lambda_{col+i}) R_s[j][i]
+            const size_t sb = p->S.size();
+            p->S.resize(sb + size_t(W) * W, 0.0f);
+            for (int i = 0; i < W; ++i) {
+                const double sl = std::sqrt(std::max(lam[size_t(col + i)], 0.0));
+                for (int j = 0; j < W; ++j)
+                    p->S[sb + size_t(i) * W + j] =
+                        float(sl * (P.rotate_segments ? R[size_t(j) * W + i] : (i == j ? 1.0 : 0.0)));
+            }
             // rows of M: R_s * V[:, col .. col+W)^T
 #pragma omp parallel for schedule(static)
             for (int j = 0; j < W; ++j) {
@@ -587,7 +621,10 @@ saq_status saq_plan_from_parts(int32_t D, int32_t n_seg, const int32_t* widths, 
         p->bits = b;
         p->M.assign(M, M + dk * D);
         p->c.assign(c, c + D);
-        if (variances) p->var.assign(variances, variances + D);
+        if (variances) {
+            p->var.assign(variances, variances + D);
+            p->S = diagonal_spread(w, b, p->var);
+        }
         saq_default_params(&p->params);
         p->params.granularity = 1;
         p->params.max_width = 0;
@@ -650,7 +687,8 @@ void saq_plan_free(saq_plan* p) { delete p; }
 // ---- serialisation --------------------------------------------------------
 // "SAQPLAN1" | u32 version | i32 D | i32 n_seg | params | f64 model_error |
 // f64 min_error | i64 quota | i64 used | i32 widths[n_seg] | i32 bits[n_seg] |
-// f32 c[D] | f64 var[D] | f32 M[D_kept x D] | u64 FNV-1a of all previous bytes
+// f32 c[D] | f64 var[D] | f32 M[D_kept x D] | i64 n_S | f32 S[n_S] |
+// u64 FNV-1a of all previous bytes.  Version 1 files end after M (no S).
 
 namespace {
 struct Writer {
@@ -689,7 +727,7 @@ saq_status saq_plan_save(const saq_plan* p, const char* path) {
     if (!p || !path) return fail(SAQ_EINVAL, "bad arguments");
     Writer w;
     w.arr(kMagic, 8);
-    w.put(uint32_t(1));
+    w.put(uint32_t(2));
     w.put(p->D);
     w.put(int32_t(p->widths.size()));
     w.put(p->params);
@@ -702,6 +740,8 @@ saq_status saq_plan_save(const saq_plan* p, const char* path) {
     w.arr(p->c.data(), p->c.size());
     w.arr(p->var.data(), p->var.size());
     w.arr(p->M.data(), p->M.size());
+    w.put(int64_t(p->S.size()));
+    w.arr(p->S.data(), p->S.size());
     w.put(fnv1a(w.buf.data(), w.buf.size()));
     FILE* f = std::fopen(path, "wb");
     if (!f) return fail(SAQ_EIO, std::string("cannot open ") + path);
@@ -727,7 +767,8 @@ saq_status saq_plan_load(const char* path, saq_plan** out) {
     Reader r{buf.data() + 8, buf.size() - 16};
     uint32_t ver; int32_t D, ns;
     std::unique_ptr<saq_plan> p(new saq_plan());
-    if (!r.get(ver) || ver != 1 || !r.get(D) || !r.get(ns) || D <= 0 || ns <= 0 || ns > D)
+    if (!r.get(ver) || (ver != 1 && ver != 2) || !r.get(D) || !r.get(ns) || D <= 0 || ns <= 0 ||
+        ns > D)
         return fail(SAQ_EIO, "bad plan header");
     p->D = D;
     if (!r.get(p->params) || !r.get(p->model_error) || !r.get(p->min_error) || !r.get(p->quota) ||
@@ -739,8 +780,16 @@ saq_status saq_plan_load(const char* path, saq_plan** out) {
     int64_t dk = 0;
     for (int s = 0; s < ns; ++s) if (p->bits[s] > 0) dk += p->widths[s];
     p->c.resize(D); p->var.resize(D); p->M.resize(size_t(dk * D));
-    if (!r.arr(p->c.data(), D) || !r.arr(p->var.data(), D) || !r.arr(p->M.data(), size_t(dk * D)) || r.i != r.n)
+    if (!r.arr(p->c.data(), D) || !r.arr(p->var.data(), D) || !r.arr(p->M.data(), size_t(dk * D)))
         return fail(SAQ_EIO, "truncated plan file");
+    if (ver >= 2) {
+        int64_t ns2 = 0, want_s = 0;
+        for (int s = 0; s < ns; ++s) if (p->bits[s] > 0) want_s += int64_t(p->widths[s]) * p->widths[s];
+        if (!r.get(ns2) || (ns2 != 0 && ns2 != want_s)) return fail(SAQ_EIO, "bad spread blocks in plan file");
+        p->S.resize(size_t(ns2));
+        if (!r.arr(p->S.data(), size_t(ns2))) return fail(SAQ_EIO, "truncated plan file");
+    }
+    if (r.i != r.n) return fail(SAQ_EIO, "trailing bytes in plan file");
     p->derive();
     *out = p.release();
     return SAQ_OK;

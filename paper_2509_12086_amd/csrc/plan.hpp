@@ -14,6 +14,8 @@ namespace saq {
 //   M_pad   float [n_pad x k_pad]   rows = kept dims in plan order, zero padded
 //   c_pad   float [k_pad]
 //   segtab  int32 [n_kept x 4]      column start, width, bits, code byte offset
+//   S       float [sum_s W_s^2]     per kept segment, row-major W x W blocks
+//                                   sqrt(sigma_i^2) R_s^T (one float if absent)
 constexpr int kGemmTileN = 128;   // GEMM tile along the kept dims
 constexpr int kGemmTileK = 32;    // GEMM tile along the input dims
 constexpr int kGemmTileM = 128;   // GEMM tile along the vectors
@@ -27,7 +29,7 @@ struct SegEntry {
 
 struct DeviceLayout {
     int32_t n_pad = 0, k_pad = 0;
-    int64_t off_M = 0, off_c = 0, off_seg = 0, bytes = 0;
+    int64_t off_M = 0, off_c = 0, off_seg = 0, off_S = 0, bytes = 0;
 };
 
 }  // namespace saq
@@ -38,6 +40,13 @@ struct saq_plan {
     std::vector<float> M;                // D_kept x D
     std::vector<float> c;                // D
     std::vector<double> var;             // D (variances sorted descending), zeros if unknown
+    // Per kept segment s (plan order) a W x W block, row-major:
+    // S_s[i][j] = sqrt(lambda_i) R_s[j][i], R_s the segment's rotation and
+    // lambda_i the variance of the PCA axis behind kept dim i.  For a query's
+    // projection q'_s = R_s P_s (q - c), (S_s q'_s)_i = sqrt(lambda_i) P_i (q - c),
+    // so ||S_s q'_s||^2 is the variance over the data of <o_s, q_s>
+    // (Section 4.3).  Empty when the variances are unknown.
+    std::vector<float> S;
     saq_plan_params params{};
     double model_error = 0.0, min_error = 0.0;
     int64_t quota = 0, used = 0;

@@ -35,6 +35,25 @@ def oracle_encode(plan, X, rounds=4, instrument=False):
     return oracle.encode(X, M, c, plan.kept_widths, plan.kept_bits, rounds, instrument)
 
 
+def oracle_records(plan, X, rounds=4):
+    """Records encoded and packed by the oracle, for the scans' parity tests:
+    (packed uint8 [n, code_bytes], factors float32 [n, k + 1], codes int32
+    [n, D_kept]).  Both sides then read the same bytes and the same FP32
+    factors, and nothing the oracle reads comes from the device."""
+    enc = oracle_encode(plan, X, rounds)
+    packed = oracle.pack(enc.codes, plan.kept_widths, plan.kept_bits)
+    fac = np.concatenate([enc.factors, enc.norm2[:, None]], axis=1).astype(np.float32)
+    return packed, fac, enc.codes
+
+
+def oracle_scan(plan, Q, codes, fac, prefix_bits=0):
+    """The oracle's Section 3.2 estimator on records given as in oracle_records."""
+    M, c, _ = plan.arrays()
+    return oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
+                           fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64),
+                           prefix_bits=prefix_bits)
+
+
 U32 = 2.0 ** -24
 
 

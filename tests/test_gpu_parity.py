@@ -11,7 +11,8 @@ import pytest
 import oracle
 import synth
 import paper_2509_12086_amd as saq
-from gpu_util import compare, cuda, gpu_encode, oracle_encode, say, to_dev
+from gpu_util import (compare, cuda, gpu_encode, oracle_encode, oracle_records, oracle_scan,
+                      say, to_dev)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -169,23 +170,25 @@ def test_encode_deterministic(cfg1):
 
 
 def test_estimate_dist(cfg1):
-    """saq_estimate_dist equals the oracle's estimator evaluated on the same
-    records (FP32 accumulation tolerance), and the relative distance error of
-    the device-encoded records is within 1 % of the oracle-encoded ones'."""
+    """saq_estimate_dist equals the oracle's estimator on the same records
+    (the oracle's, FP32 accumulation tolerance), and end to end the relative
+    distance error of device-encoded, device-scanned records is within 1 % of
+    the oracle's."""
     ds, X, plan = cfg1
     Qr = ds.queries(64)
     Xs = X[:4000]
-    packed, fac = gpu_encode(plan, Xs, 4)
+    M, c, _ = plan.arrays()
     say("estimate cfg1 64 queries x 4000 records")
+    opk, ofac, ocodes = oracle_records(plan, Xs, 4)
+    d2o = saq.estimate_dist(plan, to_dev(Qr), to_dev(opk), to_dev(ofac))
+    torch.cuda.synchronize()
+    ref = oracle_scan(plan, Qr, ocodes, ofac)
+    scale = ofac[:, -1][None, :] + ((Qr.astype(np.float64) - c) ** 2).sum(1)[:, None]
+    assert np.max(np.abs(d2o.cpu().numpy() - ref) / scale) < 2e-5
+    packed, fac = gpu_encode(plan, Xs, 4)
     d2 = saq.estimate_dist(plan, to_dev(Qr), to_dev(packed), to_dev(fac))
     torch.cuda.synchronize()
     d2 = d2.cpu().numpy()
-    M, c, _ = plan.arrays()
-    codes = saq.unpack_codes(plan, packed)
-    ref = oracle.estimate(Qr, M, c, plan.kept_widths, plan.kept_bits, codes,
-                          fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
-    scale = fac[:, -1][None, :] + ((Qr.astype(np.float64) - c) ** 2).sum(1)[:, None]
-    assert np.max(np.abs(d2 - ref) / scale) < 2e-5
     true = oracle.true_dist2(Qr, Xs)
     enc = oracle_encode(plan, Xs, 4)
     ref_o = oracle.estimate(Qr, M, c, plan.kept_widths, plan.kept_bits, enc.codes, enc.factors,
@@ -218,14 +221,12 @@ def test_estimate_dist_shapes():
         for n, nq in ((1, 1), (127, 63), (129, 65), (len(Xs), 130)):
             say(f"estimate D={plan.D} n={n} nq={nq}")
             Q = (rng.standard_normal((nq, plan.D)) * Xs.std(0)).astype(np.float32)
-            packed, fac = gpu_encode(plan, Xs[:n], 4)
+            packed, fac, codes = oracle_records(plan, Xs[:n], 4)
             d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac))
             torch.cuda.synchronize()
             d2 = d2.cpu().numpy()
             M, c, _ = plan.arrays()
-            codes = saq.unpack_codes(plan, packed)
-            ref = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
-                                  fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
+            ref = oracle_scan(plan, Q, codes, fac)
             scale = fac[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
             assert d2.shape == (nq, n)
             assert np.max(np.abs(d2 - ref) / scale) < 2e-5
@@ -248,17 +249,14 @@ def test_estimate_dist_prefix():
                                                      [16, 48, 32, 16, 16, 32])).astype(np.float32)
     for plan, Xs in ((p1, X), (pw, Xw)):
         Q = (rng.standard_normal((70, plan.D)) * Xs.std(0)).astype(np.float32)
-        packed, fac = gpu_encode(plan, Xs, 4)
+        packed, fac, codes = oracle_records(plan, Xs, 4)
         M, c, _ = plan.arrays()
-        codes = saq.unpack_codes(plan, packed)
         scale = fac[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
         for b in (1, 2, 3, 5, 8, 12):
             say(f"estimate prefix D={plan.D} b={b}")
             d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac), prefix_bits=b)
             torch.cuda.synchronize()
-            ref = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
-                                  fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64),
-                                  prefix_bits=b)
+            ref = oracle_scan(plan, Q, codes, fac, prefix_bits=b)
             assert np.max(np.abs(d2.cpu().numpy() - ref) / scale) < 2e-5, b
     packed1, fac1 = gpu_encode(p1, X[:10], 4)
     with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):

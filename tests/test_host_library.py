@@ -123,6 +123,56 @@ def test_plan_save_load_roundtrip(tmp_path):
         saq.Plan.load(str(tmp_path / "missing"))
 
 
+def _fnv1a(b: bytes) -> int:
+    h = 0xcbf29ce484222325
+    for x in b:
+        h = ((h ^ x) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_plan_file_carries_the_spread_blocks(tmp_path):
+    """The plan keeps, per kept segment, S_s = diag(sqrt(lambda)) R_s^T
+    (Section 4.3's sigma_Seg from the query's projection).  Read back from the
+    file: S_s S_s^T = diag(lambda) (R_s is orthonormal) and S_s M_s has
+    orthogonal rows of norm sqrt(lambda) (M_s = R_s P_s).  A version-1 file,
+    which has no blocks, still loads."""
+    X = synth.cfg1(3000).rows()
+    p = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=4.0, fit_sample=0))
+    path = str(tmp_path / "p.saqplan")
+    p.save(path)
+    raw = open(path, "rb").read()
+    kw = p.kept_widths
+    nS = int(sum(w * w for w in kw))
+    tail = raw[len(raw) - 8 - 4 * nS - 8: len(raw) - 8]
+    assert int(np.frombuffer(tail[:8], np.int64)[0]) == nS
+    S = np.frombuffer(tail[8:], np.float32).astype(np.float64)
+    M, _, var = p.arrays()
+    lam_kept, pos = [], 0
+    for w, b in zip(p.widths, p.bits):
+        if b > 0:
+            lam_kept.extend(var[pos:pos + w])
+        pos += w
+    lam_kept = np.asarray(lam_kept)
+    a = r = 0
+    for w in kw:
+        Sb = S[a:a + w * w].reshape(w, w)
+        lam = lam_kept[r:r + w]
+        np.testing.assert_allclose(Sb @ Sb.T, np.diag(lam), rtol=0, atol=1e-5 * lam.max())
+        SM = Sb @ M[r:r + w].astype(np.float64)
+        np.testing.assert_allclose(SM @ SM.T, np.diag(lam), rtol=0, atol=1e-5 * lam.max())
+        a += w * w
+        r += w
+    # version 1: the same file without the blocks
+    body = bytearray(raw[:len(raw) - 8 - 4 * nS - 8])
+    body[8:12] = np.uint32(1).tobytes()
+    v1 = bytes(body) + np.uint64(_fnv1a(bytes(body))).tobytes()
+    old = str(tmp_path / "v1.saqplan")
+    open(old, "wb").write(v1)
+    q = saq.Plan.load(old)
+    assert q.widths == p.widths and q.bits == p.bits
+    assert q.device_bytes() < p.device_bytes()
+
+
 def test_from_parts_and_argument_errors():
     D = 32
     M = np.eye(D, dtype=np.float32)[:24]
