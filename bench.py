@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12     # MI355X dense FP32 matrix FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
+PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix FLOP/s
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-ops/s
 
 
@@ -192,6 +193,8 @@ def main():
     cpu = None
     if not a.no_cpu and not a.kernels_only:
         cpu = cpu_baseline(plan, X, a)
+    fit = None if a.kernels_only else fit_leg(a, X, fit_rows, stream)
+    refs = None if a.kernels_only else ref_leg(a, ds, plan, X, codes, fac, ws, stream, ms_step)
     del X, O, ws, codes, fac
     torch.cuda.empty_cache()
     batched = scans = None
@@ -258,6 +261,8 @@ def main():
                                                   PEAK_FP32_MFMA / (2.0 * D * dk)),
         },
         "cpu_baseline": cpu,
+        "fit": fit,
+        "reference_vectors": refs,
         "batched": batched,
         "estimate_scan": scans,
         "serving": serving,
@@ -265,6 +270,87 @@ def main():
     }
     out["end_to_end"]["frac_of_binding"] = out["value"] / out["end_to_end"]["binding_roofline_vectors_per_s"]
     print(json.dumps(out), flush=True)
+
+
+def ref_leg(a, ds, plan, X, codes, fac, ws, stream, plain_ms):
+    """Encode with a reference vector per record (saq_encode_ref): the 1,024
+    cluster centers of the headline data as IVF list centroids, each record
+    on its nearest one (assigned outside the timed region).  Same plan and
+    launch shapes as the headline step; only the centering differs."""
+    import torch
+    import paper_2509_12086_amd as saq
+    dev = X.device
+    refs = torch.from_numpy((ds.centers @ ds.rotation.T).astype(np.float32)).to(dev)
+    rn = (refs.double() ** 2).sum(1)
+    rt = refs.double().T.contiguous()
+    ids = torch.empty(X.shape[0], dtype=torch.int32, device=dev)
+    for a0 in range(0, X.shape[0], 65536):
+        xb = X[a0:a0 + 65536].double()
+        ids[a0:a0 + xb.shape[0]] = torch.argmin(rn[None, :] - 2.0 * (xb @ rt), dim=1).to(torch.int32)
+    del rt
+    step = lambda: saq.encode(plan, X, a.rounds, codes, fac, ws, stream, refs=refs, ref_ids=ids)
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    del refs, ids
+    return {"workload": f"{X.shape[0]} x {X.shape[1]}, 1024 list centroids, nearest per record, "
+                        f"{a.bpd:g} b/dim, r={a.rounds}",
+            "ms_per_step": ms, "vectors_per_s": X.shape[0] / (ms * 1e-3),
+            "plain_ms_per_step": plain_ms}
+
+
+def fit_leg(a, X, fit_rows, stream):
+    """Section 4.1's fit with the rows on the device: mean and covariance on
+    the FP64 matrix cores, eigen-decomposition and plan search on the host.
+    Timed on the 65,536 rows the headline plan is fitted on (D = 960), against
+    the host fit of the same rows, and the covariance alone at D = 3072."""
+    import torch
+    import synth
+    import paper_2509_12086_amd as saq
+    params = saq.PlanParams(bits_per_dim=a.bpd, fit_sample=0)
+    m = fit_rows.shape[0]
+    Xs = X[:m]
+    t0 = time.time()
+    saq.Plan.fit(fit_rows, params)
+    host_s = time.time() - t0
+    saq.Plan.fit_device(Xs, params, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    saq.Plan.fit_device(Xs, params, stream=stream)
+    dev_s = time.time() - t0
+
+    def cov_ms(Y, k=3):
+        mean, cov = saq.covariance(Y, 0, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            saq.covariance(Y, 0, mean, cov, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    rows = []
+    for D, Y in ((Xs.shape[1], Xs), (3072, None)):
+        if Y is None:
+            Y = synth.cfg3(0, m).rows_torch(m, X.device)
+        ms = cov_ms(Y)
+        flop = float(m) * D * (D + 1)          # upper triangle, multiply and add
+        rows.append({"D": D, "rows": m, "covariance_ms": ms,
+                     "tflops_fp64": flop / (ms * 1e-3) / 1e12,
+                     "frac_fp64_mfma": flop / (ms * 1e-3) / PEAK_FP64_MFMA})
+        del Y
+    torch.cuda.empty_cache()
+    return {"workload": f"fit on {m} rows: D = {Xs.shape[1]} (the headline plan's rows) and "
+                        f"D = 3072 (covariance only)",
+            "host_fit_s": host_s, "device_fit_s": dev_s, "covariance": rows}
 
 
 def batched_leg(a):

@@ -97,6 +97,29 @@ void saq_default_params(saq_plan_params* p);
 saq_status saq_fit_plan(const float* X, int64_t n, int32_t D,
                         const saq_plan_params* p, saq_plan** out);
 
+/* Mean and covariance of the fit sample on the device (Section 4.1): the
+   same evenly spaced sample as saq_fit_plan (row i*n/m of X_dev for
+   i < m = fit_sample, or every row when fit_sample is 0 or >= n), X_dev
+   [n x D] FP32 row-major on the device.  mean_dev [D] FP64 is the host fit's
+   mean bit for bit (fixed 4,096-row blocks added in block order); cov_dev
+   [D x D] FP64 row-major = (1/m) sum (x - c)(x - c)^T, summed on the FP64
+   matrix cores in a fixed order (run to run identical, equal to the host's
+   covariance up to FP64 rounding).  ws_dev: saq_covariance_workspace_bytes
+   bytes.  Asynchronous on `stream`. */
+int64_t    saq_covariance_workspace_bytes(int64_t n, int32_t D, int64_t fit_sample);
+saq_status saq_covariance(const float* X_dev, int64_t n, int32_t D, int64_t fit_sample,
+                          double* mean_dev, double* cov_dev, void* ws_dev, int64_t ws_bytes,
+                          void* stream);
+
+/* saq_fit_plan with the mean and covariance from saq_covariance: the rows
+   stay on the device, the D x D covariance is copied back (the call waits
+   for `stream`), and the eigen-decomposition and plan search run on the
+   host as in saq_fit_plan.  ws_dev: saq_fit_workspace_bytes bytes. */
+int64_t    saq_fit_workspace_bytes(int64_t n, int32_t D, const saq_plan_params* p);
+saq_status saq_fit_plan_device(const float* X_dev, int64_t n, int32_t D,
+                               const saq_plan_params* p, void* ws_dev, int64_t ws_bytes,
+                               void* stream, saq_plan** out);
+
 /* Same as saq_fit_plan from a given basis: mean [D], eigenvectors [D x D]
    row-major with eigenvector j in column j, eigenvalues [D] (any order; they
    are sorted descending together with their vectors). */
@@ -144,6 +167,21 @@ int64_t    saq_encode_workspace_bytes(const saq_plan* plan, int64_t n);
 saq_status saq_encode(const saq_plan* plan, const float* X_dev, int64_t n, int32_t rounds,
                       uint8_t* codes_dev, float* factors_dev, void* ws_dev, int64_t ws_bytes,
                       void* stream);
+
+/* saq_encode with a reference vector per record instead of the plan's c
+   (Section 3.1's reference vector; the paper's experiments use the IVF
+   centroid of each vector's list): record i encodes
+     o_i = M (x_i - refs[ref_ids[i]]),  ||x_i - refs[ref_ids[i]]||^2
+   with everything else as saq_encode.  refs_dev [K x D] FP32 row-major,
+   ref_ids_dev [n] int32 on the device.  A record whose id is outside [0, K)
+   is centered on row 0 and gets a NaN norm (its last factor), so it cannot
+   pass unnoticed; nothing is read out of bounds.  The plan's M and segments
+   should come from a fit on the residuals x - refs[id].  Same workspace as
+   saq_encode.  SAQ_EINVAL for K <= 0 or null refs/ids with n > 0. */
+saq_status saq_encode_ref(const saq_plan* plan, const float* X_dev, int64_t n,
+                          const float* refs_dev, int32_t K, const int32_t* ref_ids_dev,
+                          int32_t rounds, uint8_t* codes_dev, float* factors_dev, void* ws_dev,
+                          int64_t ws_bytes, void* stream);
 
 /* Layouts of a projected-row buffer O with leading dimension ld:
    SAQ_LAYOUT_ROWS:  element (vector i, kept dim j) at O[i * ld + j], ld >= D_kept
@@ -199,6 +237,15 @@ saq_status saq_estimate_dist_prefix(const saq_plan* plan, const float* Q_dev, in
                                     int64_t n, int32_t prefix_bits, float* dist2_dev,
                                     void* ws_dev, int64_t ws_bytes, void* stream);
 
+/* saq_estimate_dist over records encoded against one reference vector ref_dev
+   [D] FP32 (one list of saq_encode_ref records, all with the same id): the
+   queries are projected as q' = M (q - ref) and ||q - ref||^2 replaces
+   ||q - c||^2.  Same workspace as saq_estimate_dist. */
+saq_status saq_estimate_dist_ref(const saq_plan* plan, const float* Q_dev, int32_t nq,
+                                 const float* ref_dev, const uint8_t* codes_dev,
+                                 const float* factors_dev, int64_t n, float* dist2_dev,
+                                 void* ws_dev, int64_t ws_bytes, void* stream);
+
 /* Multi-stage estimate with Chebyshev pruning (Section 4.3).  The kept
    segments are read in plan order (decreasing variance).  Before segment t,
    the distance of a pair (query q, record i) is bounded from below by
@@ -224,6 +271,14 @@ saq_status saq_estimate_multistage(const saq_plan* plan, const float* Q_dev, int
                                    int64_t n, const float* tau_dev, float m, float* dist2_dev,
                                    uint8_t* stage_dev, void* ws_dev, int64_t ws_bytes,
                                    void* stream);
+
+/* saq_estimate_multistage over one list of saq_encode_ref records with
+   reference ref_dev [D] (as saq_estimate_dist_ref). */
+saq_status saq_estimate_multistage_ref(const saq_plan* plan, const float* Q_dev, int32_t nq,
+                                       const float* ref_dev, const uint8_t* codes_dev,
+                                       const float* factors_dev, int64_t n, const float* tau_dev,
+                                       float m, float* dist2_dev, uint8_t* stage_dev,
+                                       void* ws_dev, int64_t ws_bytes, void* stream);
 
 /* Batched encode: many datasets, each with its own uploaded plan (uneven
    segment widths and bits), in two grouped launches for the whole batch --

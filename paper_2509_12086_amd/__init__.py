@@ -56,7 +56,9 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_plan_load", "saq_plan_free", "saq_plan_device_bytes", "saq_plan_upload",
            "saq_encode_workspace_bytes", "saq_encode", "saq_project", "saq_quantize",
            "saq_estimate_workspace_bytes", "saq_estimate_dist", "saq_estimate_dist_prefix",
-           "saq_estimate_multistage",
+           "saq_estimate_multistage", "saq_covariance_workspace_bytes", "saq_covariance",
+           "saq_encode_ref", "saq_estimate_dist_ref", "saq_estimate_multistage_ref",
+           "saq_fit_workspace_bytes", "saq_fit_plan_device",
            "saq_encode_batched_workspace_bytes",
            "saq_encode_batched", "saq_last_error", "saq_version")
 
@@ -106,6 +108,14 @@ def lib() -> ctypes.CDLL:
         "saq_estimate_dist_prefix": (i32, [P, P, i32, P, P, i64, i32, P, P, i64, P]),
         "saq_estimate_multistage": (i32, [P, P, i32, P, P, i64, P, ctypes.c_float, P, P, P, i64,
                                           P]),
+        "saq_covariance_workspace_bytes": (i64, [i64, i32, i64]),
+        "saq_encode_ref": (i32, [P, P, i64, P, i32, P, i32, P, P, P, i64, P]),
+        "saq_estimate_dist_ref": (i32, [P, P, i32, P, P, P, i64, P, P, i64, P]),
+        "saq_estimate_multistage_ref": (i32, [P, P, i32, P, P, P, i64, P, ctypes.c_float, P, P,
+                                              P, i64, P]),
+        "saq_covariance": (i32, [P, i64, i32, i64, P, P, P, i64, P]),
+        "saq_fit_workspace_bytes": (i64, [i64, i32, P]),
+        "saq_fit_plan_device": (i32, [P, i64, i32, P, P, i64, P, P]),
         "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
         "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
         "saq_last_error": (ctypes.c_char_p, []),
@@ -192,6 +202,26 @@ class Plan:
         h = ctypes.c_void_p()
         _check(lib().saq_fit_plan(_np_ptr(X), X.shape[0], X.shape[1], ctypes.byref(p),
                                   ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def fit_device(cls, X, params: Optional[PlanParams] = None, workspace=None,
+                   stream=None) -> "Plan":
+        """saq_fit_plan_device: the fit with the rows on the device (CUDA
+        float32 [n, D]); mean and covariance on the GPU, the rest on the host."""
+        torch = _torch()
+        _require_cuda_f32(X, "X")
+        n, D = X.shape
+        p = (params or PlanParams())._c()
+        need = int(lib().saq_fit_workspace_bytes(n, D, ctypes.byref(p)))
+        if need < 0:
+            raise ValueError("bad fit sizes")
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+        h = ctypes.c_void_p()
+        _check(lib().saq_fit_plan_device(_dev_ptr(X), n, D, ctypes.byref(p), _dev_ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream_ptr(stream, X.device), ctypes.byref(h)))
         return cls(h.value)
 
     @classmethod
@@ -306,8 +336,11 @@ def _alloc_out(plan: Plan, n: int, device, codes=None, factors=None):
     return codes, factors
 
 
-def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=None, stream=None):
-    """saq_encode: returns (codes uint8 [n, code_bytes], factors f32 [n, n_factors])."""
+def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=None, stream=None,
+           refs=None, ref_ids=None):
+    """saq_encode: returns (codes uint8 [n, code_bytes], factors f32 [n, n_factors]).
+    With refs (CUDA float32 [K, D]) and ref_ids (CUDA int32 [n]),
+    saq_encode_ref: record i is encoded against refs[ref_ids[i]]."""
     torch = _torch()
     _require_cuda_f32(X, "X", plan.D)
     n = X.shape[0]
@@ -315,10 +348,26 @@ def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=N
     need = plan.encode_workspace_bytes(n)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
-    _check(lib().saq_encode(plan._h, _dev_ptr(X), n, rounds, _dev_ptr(codes), _dev_ptr(factors),
-                            _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
-                            _stream_ptr(stream, X.device)))
+    if refs is None:
+        _check(lib().saq_encode(plan._h, _dev_ptr(X), n, rounds, _dev_ptr(codes), _dev_ptr(factors),
+                                _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream, X.device)))
+        return codes, factors
+    _require_cuda_f32(refs, "refs", plan.D)
+    if not (isinstance(ref_ids, torch.Tensor) and ref_ids.is_cuda and ref_ids.dtype == torch.int32
+            and ref_ids.shape == (n,) and ref_ids.is_contiguous()):
+        raise ValueError("ref_ids must be a contiguous CUDA int32 tensor [n]")
+    _check(lib().saq_encode_ref(plan._h, _dev_ptr(X), n, _dev_ptr(refs), refs.shape[0],
+                                _dev_ptr(ref_ids), rounds, _dev_ptr(codes), _dev_ptr(factors),
+                                _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream, X.device)))
     return codes, factors
+
+
+def _require_ref(plan: Plan, ref, Q):
+    _require_cuda_f32(ref, "ref", ndim=1)
+    if ref.shape[0] != plan.D or ref.device != Q.device:
+        raise ValueError("ref must be a CUDA float32 [D] tensor on Q's device")
 
 
 def _layout_ld(O, layout: int) -> int:
@@ -389,11 +438,22 @@ def _scan_buffers(plan: Plan, Q, codes, factors, out, workspace):
 
 
 def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, stream=None,
-                  prefix_bits: int = 0):
+                  prefix_bits: int = 0, ref=None):
     """saq_estimate_dist: estimated squared distances f32 [nq, n]; with
     prefix_bits > 0, saq_estimate_dist_prefix (each segment's first
-    min(prefix_bits, B) bits only)."""
+    min(prefix_bits, B) bits only); with ref (CUDA float32 [D]),
+    saq_estimate_dist_ref over records encoded against that reference."""
     nq, n, out, workspace = _scan_buffers(plan, Q, codes, factors, out, workspace)
+    if ref is not None:
+        if prefix_bits:
+            raise ValueError("prefix_bits and ref do not combine")
+        _require_ref(plan, ref, Q)
+        _check(lib().saq_estimate_dist_ref(plan._h, _dev_ptr(Q), nq, _dev_ptr(ref),
+                                           _dev_ptr(codes), _dev_ptr(factors), n, _dev_ptr(out),
+                                           _dev_ptr(workspace),
+                                           workspace.numel() * workspace.element_size(),
+                                           _stream_ptr(stream, Q.device)))
+        return out
     _check(lib().saq_estimate_dist_prefix(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes),
                                           _dev_ptr(factors), n, int(prefix_bits), _dev_ptr(out),
                                           _dev_ptr(workspace),
@@ -403,7 +463,7 @@ def estimate_dist(plan: Plan, Q, codes, factors, out=None, workspace=None, strea
 
 
 def estimate_multistage(plan: Plan, Q, codes, factors, tau, m: float = 4.0, out=None,
-                        stage=None, workspace=None, stream=None):
+                        stage=None, workspace=None, stream=None, ref=None):
     """saq_estimate_multistage (Section 4.3): returns (dist2 f32 [nq, n],
     stage u8 [nq, n]).  tau: CUDA float32 [nq] thresholds; a pair whose lower
     bound before segment t exceeds its query's threshold gets that bound and
@@ -418,12 +478,46 @@ def estimate_multistage(plan: Plan, Q, codes, factors, tau, m: float = 4.0, out=
     if stage.shape != (nq, n) or stage.dtype != torch.uint8 or not stage.is_contiguous() \
             or not stage.is_cuda:
         raise ValueError("stage must be a contiguous CUDA uint8 tensor [nq, n]")
+    if ref is not None:
+        _require_ref(plan, ref, Q)
+        _check(lib().saq_estimate_multistage_ref(plan._h, _dev_ptr(Q), nq, _dev_ptr(ref),
+                                                 _dev_ptr(codes), _dev_ptr(factors), n,
+                                                 _dev_ptr(tau), float(m), _dev_ptr(out),
+                                                 _dev_ptr(stage), _dev_ptr(workspace),
+                                                 workspace.numel() * workspace.element_size(),
+                                                 _stream_ptr(stream, Q.device)))
+        return out, stage
     _check(lib().saq_estimate_multistage(plan._h, _dev_ptr(Q), nq, _dev_ptr(codes),
                                          _dev_ptr(factors), n, _dev_ptr(tau), float(m),
                                          _dev_ptr(out), _dev_ptr(stage), _dev_ptr(workspace),
                                          workspace.numel() * workspace.element_size(),
                                          _stream_ptr(stream, Q.device)))
     return out, stage
+
+
+def covariance(X, fit_sample: int = 0, mean=None, cov=None, workspace=None, stream=None):
+    """saq_covariance: (mean f64 [D], covariance f64 [D, D]) of the fit
+    sample of the device rows X (CUDA float32 [n, D])."""
+    torch = _torch()
+    _require_cuda_f32(X, "X")
+    n, D = X.shape
+    if mean is None:
+        mean = torch.empty(D, dtype=torch.float64, device=X.device)
+    if cov is None:
+        cov = torch.empty((D, D), dtype=torch.float64, device=X.device)
+    for t, shape, name in ((mean, (D,), "mean"), (cov, (D, D), "cov")):
+        if tuple(t.shape) != shape or t.dtype != torch.float64 or not t.is_contiguous() \
+                or t.device != X.device:
+            raise ValueError(f"{name} must be a contiguous float64 tensor {shape} on X's device")
+    need = int(lib().saq_covariance_workspace_bytes(n, D, int(fit_sample)))
+    if need < 0:
+        raise ValueError("bad covariance sizes")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=X.device)
+    _check(lib().saq_covariance(_dev_ptr(X), n, D, int(fit_sample), _dev_ptr(mean), _dev_ptr(cov),
+                                _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
+                                _stream_ptr(stream, X.device)))
+    return mean, cov
 
 
 def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:

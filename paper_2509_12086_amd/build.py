@@ -37,10 +37,12 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     host_o = os.path.join(BUILD, "host.o")
     dev_o = os.path.join(BUILD, "device.o")
+    fit_o = os.path.join(BUILD, "fit.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "host.cpp"), "-o", host_o])
     _run([hipcc(), *HIP_FLAGS, "-c", os.path.join(CSRC, "device.hip"), "-o", dev_o])
+    _run([hipcc(), *HIP_FLAGS, "-c", os.path.join(CSRC, "fit.hip"), "-o", fit_o])
     tmp = LIB + ".tmp"
-    _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", host_o, dev_o, "-o", tmp,
+    _run([hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", host_o, dev_o, fit_o, "-o", tmp,
           "-lgomp"])
     os.replace(tmp, LIB)
     return LIB

@@ -56,6 +56,17 @@ template <int BI> constexpr int gemm_lds_floats() { return 2 * (64 * BI + TN) * 
 
 // One (64 BI) x 128 output tile (tile_m, tile_n).  lds: gemm_lds_floats<BI>()
 // floats, free on entry and on return (the last k-step ends with a barrier).
+// Per-record reference vectors (Section 3.1's c; the IVF centroid of each
+// record's list in the paper's experiments): record i is centered on row
+// ids[i] of refs [K x D] (all records on row 0 when ids is null) instead of
+// the plan's c.  A record whose id is outside [0, K) is centered on row 0 and
+// gets a NaN norm, so its factors show it.
+struct RefRows {
+    const float* refs;   // null: the plan's c
+    const int32_t* ids;
+    int32_t K;
+};
+
 // FULLB: both of the wave's 32-column blocks hold kept dims.  Without it
 // (a wave of the last column tile whose second block lies past dk) the wave
 // runs only its first block's MFMAs; the waves of one workgroup may take
@@ -64,7 +75,7 @@ template <int LAYOUT, bool ACC64, bool NORM, int BI, bool FULLB = true>
 __device__ __forceinline__ void gemm_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
     static_assert(BI == 1 || BI == 2, "tile shapes: 64 x 128 or 128 x 128");
     constexpr int RM = gemm_rows<BI>();          // vectors per tile
     constexpr int ATPR = 256 / RM;               // threads per A row (4 or 2)
@@ -84,6 +95,14 @@ __device__ __forceinline__ void gemm_tile_impl(
     // rows past n read row n-1 (always valid memory) and are zeroed on store
     const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
     const float* brow = Mp + int64_t(n0 + br) * k_pad;
+    // this row's reference: the plan's c (zero padded to k_pad) or its row of refs
+    const float* crow = cp;
+    bool ref_bad = false;
+    if (R.refs != nullptr) {
+        const int32_t id = R.ids != nullptr ? R.ids[arow_ok ? arow : n - 1] : 0;
+        ref_bad = id < 0 || id >= R.K;
+        crow = R.refs + int64_t(ref_bad ? 0 : id) * D;
+    }
     double nacc = 0.0;
 
     // raw global values of the next tile; consumed only after the MFMAs of
@@ -94,7 +113,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 #pragma unroll
         for (int q = 0; q < ALK / 4; ++q) {
             const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
-            const float4 c4 = *reinterpret_cast<const float4*>(cp + kb + 4 * q);
+            const float4 c4 = *reinterpret_cast<const float4*>(crow + kb + 4 * q);
             rx[4 * q + 0] = x4.x; rx[4 * q + 1] = x4.y; rx[4 * q + 2] = x4.z; rx[4 * q + 3] = x4.w;
             rc[4 * q + 0] = c4.x; rc[4 * q + 1] = c4.y; rc[4 * q + 2] = c4.z; rc[4 * q + 3] = c4.w;
         }
@@ -109,7 +128,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 #pragma unroll
         for (int e = 0; e < ALK; ++e) {
             rx[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
-            rc[e] = cp[kb + e];
+            rc[e] = (kb + e < D) ? crow[kb + e] : 0.f;
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) rb[e] = brow[k0 + bk + e];
@@ -212,7 +231,7 @@ __device__ __forceinline__ void gemm_tile_impl(
         // the ATPR threads of a row are adjacent lanes
         if (ATPR >= 2) nacc += __shfl_xor(nacc, 1);
         if (ATPR >= 4) nacc += __shfl_xor(nacc, 2);
-        if ((t % ATPR) == 0 && arow_ok) norm2[arow] = float(nacc);
+        if ((t % ATPR) == 0 && arow_ok) norm2[arow] = ref_bad ? __builtin_nanf("") : float(nacc);
     }
 
     // epilogue: lane holds column n0 + wn*64 + 32*bj + li and, for register
@@ -269,19 +288,19 @@ template <int LAYOUT, bool ACC64, int BI>
 __device__ __forceinline__ void gemm_tile(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds) {
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
     // the wave's second 32-column block (wave w covers columns
     // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
     const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
     if (norm2 != nullptr && tile_n == 0)
         gemm_tile_impl<LAYOUT, ACC64, true, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
-                                                tile_m, tile_n, lds);
+                                                tile_m, tile_n, lds, R);
     else if (fullb)
         gemm_tile_impl<LAYOUT, ACC64, false, BI, true>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                       norm2, tile_m, tile_n, lds);
+                                                       norm2, tile_m, tile_n, lds, R);
     else
         gemm_tile_impl<LAYOUT, ACC64, false, BI, false>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                        norm2, tile_m, tile_n, lds);
+                                                        norm2, tile_m, tile_n, lds, R);
 }
 
 // FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
@@ -291,7 +310,7 @@ template <bool VEC, int LAYOUT, bool ACC64>
 __global__ __launch_bounds__(256) void project_kernel(
     const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
     const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tiles_m, int tiles_n) {
+    float* __restrict__ norm2, int tiles_m, int tiles_n, RefRows R) {
     constexpr int BI = gemm_bi<ACC64>();
     __shared__ __attribute__((aligned(16))) float lds[gemm_lds_floats<BI>()];
     const int bid = blockIdx.x;
@@ -300,7 +319,7 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int tile_m = (local / tiles_n) * NXCD + xcd;
     if (tile_m >= tiles_m) return;
     gemm_tile<LAYOUT, ACC64, BI>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n,
-                                 lds);
+                                 lds, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -618,10 +637,12 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) 
     // without them accumulate in FP32 on the same tile
     if (S.acc64)
         gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
-                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds);
+                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds,
+                                          RefRows{nullptr, nullptr, 0});
     else
         gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
-                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds);
+                                          S.O, S.ld, S.norm2, tile_m, tile_n, lds,
+                                          RefRows{nullptr, nullptr, 0});
 }
 
 struct QuantSet {
@@ -980,20 +1001,22 @@ const float* dev_S(const saq_plan* p) {
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O, int64_t ld,
-                          int layout, float* norm2, hipStream_t st) {
+                          int layout, float* norm2, hipStream_t st,
+                          RefRows R = RefRows{nullptr, nullptr, 0}) {
     const int rows = p->acc64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
     const int tiles_m = int((n + rows - 1) / rows);
     const int tiles_n = p->layout.n_pad / TN;
     const int slots = (tiles_m + NXCD - 1) / NXCD;
     const dim3 grid(unsigned(NXCD * slots * tiles_n));
-    const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
+    const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
+                     ((reinterpret_cast<uintptr_t>(R.refs) & 15) == 0);
     if (layout == LAYOUT_DIMS && ((reinterpret_cast<uintptr_t>(O) & 15) != 0 || (ld % 4) != 0))
         return saq::fail(SAQ_EINVAL, "dims-major output needs a 16-byte aligned buffer and ld % 4 == 0");
     if (layout == LAYOUT_TILES && (reinterpret_cast<uintptr_t>(O) & 15) != 0)
         return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
 #define SAQ_LAUNCH_PROJ(V, L, A)                                                                  \
     hipLaunchKernelGGL((project_kernel<V, L, A>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),   \
-                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n)
+                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R)
 #define SAQ_LAUNCH_PROJ2(V, L) \
     do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true); else SAQ_LAUNCH_PROJ(V, L, false); } while (0)
     if (layout == LAYOUT_TILES) {
@@ -1186,8 +1209,11 @@ saq_status saq_quantize(const saq_plan* p, const float* O, int64_t ld, int32_t l
                            static_cast<hipStream_t>(stream));
 }
 
-saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
-                      uint8_t* codes, float* factors, void* ws, int64_t ws_bytes, void* stream) {
+}  // extern "C"
+
+static saq_status encode_impl(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
+                              uint8_t* codes, float* factors, void* ws, int64_t ws_bytes,
+                              void* stream, RefRows R) {
     if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
     if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (n == 0) return SAQ_OK;
@@ -1200,9 +1226,26 @@ saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t roun
     float* nrm = reinterpret_cast<float*>(base + round_up(enc_o_bytes(p, n), 256));
     // with nothing kept the projection kernel still runs its first column
     // tile (all padding) to produce ||x - c||^2
-    saq_status s = launch_project(p, X, n, O, ld, LAYOUT_TILES, nrm, st);
+    saq_status s = launch_project(p, X, n, O, ld, LAYOUT_TILES, nrm, st, R);
     if (s != SAQ_OK) return s;
     return launch_quantize(p, O, ld, LAYOUT_TILES, n, nrm, rounds, codes, factors, st);
+}
+
+extern "C" {
+
+saq_status saq_encode(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
+                      uint8_t* codes, float* factors, void* ws, int64_t ws_bytes, void* stream) {
+    return encode_impl(p, X, n, rounds, codes, factors, ws, ws_bytes, stream,
+                       RefRows{nullptr, nullptr, 0});
+}
+
+saq_status saq_encode_ref(const saq_plan* p, const float* X, int64_t n, const float* refs,
+                          int32_t K, const int32_t* ref_ids, int32_t rounds, uint8_t* codes,
+                          float* factors, void* ws, int64_t ws_bytes, void* stream) {
+    if (K <= 0) return saq::fail(SAQ_EINVAL, "K must be positive");
+    if (n > 0 && (!refs || !ref_ids)) return saq::fail(SAQ_EINVAL, "null reference buffer");
+    return encode_impl(p, X, n, rounds, codes, factors, ws, ws_bytes, stream,
+                       RefRows{refs, ref_ids, K});
 }
 
 int64_t saq_encode_batched_workspace_bytes(const saq_batch_item* items, int32_t count,
@@ -1246,10 +1289,12 @@ int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     return q * std::max(p->D_kept, 1) * 4 + q * 4 + 2 * q * std::max(p->n_kept, 1) * 4 + 512;
 }
 
-saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t nq,
-                                    const uint8_t* codes, const float* factors, int64_t n,
-                                    int32_t prefix_bits, float* out, void* ws, int64_t ws_bytes,
-                                    void* stream) {
+}  // extern "C"
+
+static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const float* ref,
+                            const uint8_t* codes, const float* factors, int64_t n,
+                            int32_t prefix_bits, float* out, void* ws, int64_t ws_bytes,
+                            void* stream) {
     if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
     if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (prefix_bits < 0) return saq::fail(SAQ_EINVAL, "prefix_bits < 0");
@@ -1260,7 +1305,8 @@ saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t n
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
     float* Qp = reinterpret_cast<float*>(base);
     float* qn2 = Qp + int64_t(nq) * std::max(p->D_kept, 1);
-    saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st);
+    saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st,
+                                  RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
     hipLaunchKernelGGL(estimate_kernel<false>, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1),
@@ -1270,10 +1316,11 @@ saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t n
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
 
-saq_status saq_estimate_multistage(const saq_plan* p, const float* Q, int32_t nq,
-                                   const uint8_t* codes, const float* factors, int64_t n,
-                                   const float* tau, float m, float* out, uint8_t* stage, void* ws,
-                                   int64_t ws_bytes, void* stream) {
+
+static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq, const float* ref,
+                                  const uint8_t* codes, const float* factors, int64_t n,
+                                  const float* tau, float m, float* out, uint8_t* stage, void* ws,
+                                  int64_t ws_bytes, void* stream) {
     if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
     if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (!(m >= 0.f) || !std::isfinite(m)) return saq::fail(SAQ_EINVAL, "m must be finite and >= 0");
@@ -1296,7 +1343,7 @@ saq_status saq_estimate_multistage(const saq_plan* p, const float* Q, int32_t nq
     float* qn2 = Qp + int64_t(nq) * dk;
     float* sig = qn2 + nq;
     float* lbq = sig + int64_t(nq) * p->n_kept;
-    saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st);
+    saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st, RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
     hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq)), dim3(256), 0, st, Qp, dk,
                        dev_seg(p), p->n_kept, dev_S(p), sig);
@@ -1313,10 +1360,44 @@ saq_status saq_estimate_multistage(const saq_plan* p, const float* Q, int32_t nq
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
 
+extern "C" {
+
+saq_status saq_estimate_multistage(const saq_plan* p, const float* Q, int32_t nq,
+                                   const uint8_t* codes, const float* factors, int64_t n,
+                                   const float* tau, float m, float* out, uint8_t* stage, void* ws,
+                                   int64_t ws_bytes, void* stream) {
+    return multistage_impl(p, Q, nq, nullptr, codes, factors, n, tau, m, out, stage, ws, ws_bytes,
+                           stream);
+}
+
+saq_status saq_estimate_multistage_ref(const saq_plan* p, const float* Q, int32_t nq,
+                                       const float* ref, const uint8_t* codes,
+                                       const float* factors, int64_t n, const float* tau, float m,
+                                       float* out, uint8_t* stage, void* ws, int64_t ws_bytes,
+                                       void* stream) {
+    if (!ref && nq > 0 && n > 0) return saq::fail(SAQ_EINVAL, "null reference");
+    return multistage_impl(p, Q, nq, ref, codes, factors, n, tau, m, out, stage, ws, ws_bytes,
+                           stream);
+}
+
+saq_status saq_estimate_dist_prefix(const saq_plan* p, const float* Q, int32_t nq,
+                                    const uint8_t* codes, const float* factors, int64_t n,
+                                    int32_t prefix_bits, float* out, void* ws, int64_t ws_bytes,
+                                    void* stream) {
+    return scan_impl(p, Q, nq, nullptr, codes, factors, n, prefix_bits, out, ws, ws_bytes, stream);
+}
+
 saq_status saq_estimate_dist(const saq_plan* p, const float* Q, int32_t nq, const uint8_t* codes,
                              const float* factors, int64_t n, float* out, void* ws,
                              int64_t ws_bytes, void* stream) {
-    return saq_estimate_dist_prefix(p, Q, nq, codes, factors, n, 0, out, ws, ws_bytes, stream);
+    return scan_impl(p, Q, nq, nullptr, codes, factors, n, 0, out, ws, ws_bytes, stream);
+}
+
+saq_status saq_estimate_dist_ref(const saq_plan* p, const float* Q, int32_t nq, const float* ref,
+                                 const uint8_t* codes, const float* factors, int64_t n, float* out,
+                                 void* ws, int64_t ws_bytes, void* stream) {
+    if (!ref && nq > 0 && n > 0) return saq::fail(SAQ_EINVAL, "null reference");
+    return scan_impl(p, Q, nq, ref, codes, factors, n, 0, out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

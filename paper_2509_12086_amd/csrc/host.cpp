@@ -481,6 +481,17 @@ static saq_status make_plan(int32_t D, const std::vector<double>& mean, const st
     return SAQ_OK;
 }
 
+saq_status plan_from_moments(int32_t D, const std::vector<double>& mean, std::vector<double> C,
+                             const saq_plan_params& P, saq_plan** out) {
+    try {
+        std::vector<double> lam, V;
+        if (!sym_eigen(C, D, lam, V)) return fail(SAQ_EINVAL, "eigen-decomposition did not converge");
+        return make_plan(D, mean, V, lam, P, out);
+    } catch (const std::bad_alloc&) {
+        return fail(SAQ_ENOMEM, "out of host memory");
+    }
+}
+
 }  // namespace saq
 
 using namespace saq;
@@ -597,9 +608,7 @@ saq_status saq_fit_plan(const float* X, int64_t n, int32_t D, const saq_plan_par
                 C[size_t(i) * D + j] = v;
                 C[size_t(j) * D + i] = v;
             }
-        std::vector<double> lam, V;
-        if (!sym_eigen(C, D, lam, V)) return fail(SAQ_EINVAL, "eigen-decomposition did not converge");
-        return make_plan(D, mu, V, lam, *p, out);
+        return plan_from_moments(D, mu, C, *p, out);
     } catch (const std::bad_alloc&) {
         return fail(SAQ_ENOMEM, "out of host memory");
     }

@@ -71,4 +71,8 @@ void set_error(const std::string& msg);
 saq_status fail(saq_status st, const std::string& msg);
 DeviceLayout device_layout(const saq_plan& p);
 void build_staging(saq_plan& p);
+// Eigen-decomposition of the covariance C [D x D] (row-major, symmetric),
+// then the plan search and projection of the fit (Sections 4.1-4.2).
+saq_status plan_from_moments(int32_t D, const std::vector<double>& mean, std::vector<double> C,
+                             const saq_plan_params& P, saq_plan** out);
 }  // namespace saq

@@ -1,0 +1,91 @@
+"""Device fit (Section 4.1) vs the oracle's PCA, through the C ABI.
+
+The mean and covariance of the fit sample come from the device; the oracle
+computes them in FP64 with numpy on the same sample rows.  Both are FP64
+sums of the same products, so they agree to FP64 rounding: the mean within
+1e-12 and the covariance within 1e-10 of its largest entry.  The plan fitted
+from the device moments must then be the oracle's plan: the same segments
+and bits (Algorithm 2 on the oracle's eigenvalues), variances within 1e-9,
+and every kept segment spanning the oracle's eigenvectors (the projector
+M_s^T M_s, which the per-segment rotation leaves unchanged, within the FP32
+rounding of M)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2509_12086_amd as saq
+from gpu_util import say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _sample(X, fit_sample):
+    n = X.shape[0]
+    m = fit_sample if 0 < fit_sample < n else n
+    rows = np.arange(m, dtype=np.int64) if m == n else (np.arange(m, dtype=np.int64) * n) // m
+    return X[rows]
+
+
+CASES = [
+    ("cfg1 10000 x 128", lambda: synth.cfg1(10_000).rows(), 0),
+    ("D=99 exp spectrum, 1 row in 3", lambda: (
+        (np.random.default_rng(9).standard_normal((30_000, 99)) * np.exp(-np.arange(99) / 30.0))
+        @ synth.haar_rotation(99, 5).T + 3.0).astype(np.float32), 10_000),
+    ("cfg2 shape 20000 x 960", lambda: synth.cfg2(20_000).rows(), 0),
+]
+
+
+@pytest.mark.parametrize("label,make,fit_sample", CASES, ids=[c[0] for c in CASES])
+def test_covariance_matches_oracle(label, make, fit_sample):
+    X = make()
+    say(f"covariance {label} fit_sample={fit_sample}")
+    mean, cov = saq.covariance(to_dev(X), fit_sample)
+    mean2, cov2 = saq.covariance(to_dev(X), fit_sample)
+    torch.cuda.synchronize()
+    assert torch.equal(mean, mean2) and torch.equal(cov, cov2)          # run to run
+    mean, cov = mean.cpu().numpy(), cov.cpu().numpy()
+    c, C, _, _ = oracle.pca(_sample(X, fit_sample))
+    assert np.array_equal(cov, cov.T)
+    assert np.max(np.abs(mean - c)) <= 1e-12 * np.max(np.abs(X))
+    err = np.max(np.abs(cov - C)) / np.max(np.abs(C))
+    say(f"  max |cov - oracle| / max|cov| = {err:.2e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("label,make,fit_sample", CASES[:2], ids=[c[0] for c in CASES[:2]])
+def test_device_fit_is_the_oracle_plan(label, make, fit_sample):
+    X = make()
+    params = saq.PlanParams(bits_per_dim=3.0, fit_sample=fit_sample)
+    say(f"device fit {label}")
+    p = saq.Plan.fit_device(to_dev(X), params)
+    _, _, lam, V = oracle.pca(_sample(X, fit_sample))
+    ref = oracle.plan_search(lam, 3.0, params.granularity, params.max_bits, params.max_width)
+    assert p.widths == ref.widths and p.bits == ref.bits
+    M, c, var = p.arrays()
+    np.testing.assert_allclose(var, lam, rtol=1e-9, atol=1e-12 * lam[0])
+    pos = row = 0
+    for w, b in zip(p.widths, p.bits):
+        if b > 0:
+            Ms = M[row:row + w].astype(np.float64)
+            Vs = V[:, pos:pos + w]
+            err = np.max(np.abs(Ms.T @ Ms - Vs @ Vs.T))
+            assert err < 1e-5, (w, b, err)
+            row += w
+        pos += w
+    # the host fit of the same rows gives the same plan
+    h = saq.Plan.fit(X, params)
+    assert h.widths == p.widths and h.bits == p.bits
+    assert np.array_equal(h.arrays()[1], c)            # the same mean, to the bit
+
+
+def test_fit_argument_errors():
+    X = to_dev(np.zeros((100, 16), np.float32))
+    with pytest.raises(ValueError):
+        saq.covariance(X, -1)
+    small = torch.empty(16, dtype=torch.uint8, device=X.device)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.covariance(X, 0, workspace=small)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.Plan.fit_device(X, saq.PlanParams(), workspace=small)

@@ -1,0 +1,128 @@
+"""Per-record reference vectors (Section 3.1's c as the IVF centroid of each
+record's list, the paper's experimental setting), through the C ABI.
+
+Records of list k are encoded against reference k: o = M (x - c_k).  The
+oracle encodes each list with its own c (its encoder takes one reference per
+call), and the device's records must meet the usual bar.  Scans of one list
+use that list's reference for the queries, checked against the oracle's
+estimator and multi-stage estimator with the same c on oracle-encoded
+records."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+import paper_2509_12086_amd as saq
+from gpu_util import compare, cuda, say, to_dev
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+K = 64
+
+
+@pytest.fixture(scope="module")
+def lists():
+    ds = synth.cfg2(12_000)
+    X = ds.rows()
+    refs = (ds.centers[:K] @ ds.rotation.T).astype(np.float32)
+    d2 = (X.astype(np.float64) ** 2).sum(1)[:, None] - 2 * X.astype(np.float64) @ refs.T.astype(np.float64) \
+        + (refs.astype(np.float64) ** 2).sum(1)[None, :]
+    ids = np.argmin(d2, axis=1).astype(np.int32)
+    R = X.astype(np.float64) - refs[ids]
+    mean, _, lam, V = oracle.pca(R)
+    # residuals are centred on their list's reference, so the plan's own c is 0
+    plan = saq.Plan.from_basis(np.zeros_like(mean), V, lam,
+                               saq.PlanParams(bits_per_dim=4.0)).upload(0)
+    return dict(ds=ds, X=X, refs=refs, ids=ids, plan=plan, V=V, lam=lam)
+
+
+def _oracle_by_list(plan, X, refs, ids, rounds=4):
+    """Oracle records in the original order, each list encoded against its c."""
+    M, _, _ = plan.arrays()
+    n, dk = X.shape[0], plan.D_kept
+    k = len(plan.kept_widths)
+    codes = np.zeros((n, dk), np.int32)
+    fac = np.zeros((n, k))
+    nn = np.zeros(n)
+    O = np.zeros((n, dk))
+    for r in np.unique(ids):
+        sel = np.nonzero(ids == r)[0]
+        e = oracle.encode(X[sel], M, refs[r], plan.kept_widths, plan.kept_bits, rounds)
+        codes[sel], fac[sel], nn[sel], O[sel] = e.codes, e.factors, e.norm2, e.O
+    return oracle.Encoded(codes, fac, nn, O)
+
+
+def test_encode_with_references_matches_oracle(lists):
+    S = lists
+    plan, X, refs, ids = S["plan"], S["X"], S["refs"], S["ids"]
+    say(f"encode_ref n={len(X)} K={K} D={plan.D}")
+    codes, fac = saq.encode(plan, to_dev(X), 4, refs=to_dev(refs), ref_ids=to_dev(ids))
+    torch.cuda.synchronize()
+    ref = _oracle_by_list(plan, X, refs, ids)
+    compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, label="ref lists")
+    # ragged n and every record on its list's reference, not the plan's c
+    n = 777
+    c2, f2 = saq.encode(plan, to_dev(X[:n]), 4, refs=to_dev(refs), ref_ids=to_dev(ids[:n]))
+    torch.cuda.synchronize()
+    assert torch.equal(c2, codes[:n]) and torch.equal(f2, fac[:n])
+
+
+def test_out_of_range_ids_give_nan_norms(lists):
+    S = lists
+    plan, X, refs = S["plan"], S["X"][:300], S["refs"]
+    ids = S["ids"][:300].copy()
+    ids[[3, 100, 299]] = [-1, K, 1 << 30]
+    _, fac = saq.encode(plan, to_dev(X), 4, refs=to_dev(refs), ref_ids=to_dev(ids))
+    torch.cuda.synchronize()
+    last = fac[:, -1].cpu().numpy()
+    bad = np.zeros(300, bool)
+    bad[[3, 100, 299]] = True
+    assert np.all(np.isnan(last[bad])) and np.all(np.isfinite(last[~bad]))
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):        # K = 0
+        saq._check(saq.lib().saq_encode_ref(plan._h, to_dev(X).data_ptr(), 300,
+                                            to_dev(refs).data_ptr(), 0, to_dev(ids).data_ptr(), 4,
+                                            None, None, None, 0, None))
+
+
+def test_scans_of_one_list(lists):
+    S = lists
+    plan, X, refs, ids = S["plan"], S["X"], S["refs"], S["ids"]
+    M, _, _ = plan.arrays()
+    r = int(np.bincount(ids).argmax())
+    Xk = X[ids == r]
+    say(f"list {r}: {len(Xk)} records")
+    e = oracle.encode(Xk, M, refs[r], plan.kept_widths, plan.kept_bits, 4)
+    packed = oracle.pack(e.codes, plan.kept_widths, plan.kept_bits)
+    fac = np.concatenate([e.factors, e.norm2[:, None]], 1).astype(np.float32)
+    Q = (refs[r] + 0.5 * (S["ds"].queries(70) - S["ds"].queries(70).mean(0))).astype(np.float32)
+    d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac), ref=to_dev(refs[r]))
+    torch.cuda.synchronize()
+    f64 = fac.astype(np.float64)
+    want = oracle.estimate(Q, M, refs[r], plan.kept_widths, plan.kept_bits, e.codes,
+                           f64[:, :-1], f64[:, -1])
+    scale = f64[:, -1][None, :] + ((Q.astype(np.float64) - refs[r]) ** 2).sum(1)[:, None]
+    assert np.max(np.abs(d2.cpu().numpy() - want) / scale) < 2e-5
+    # multi-stage over the list, with the kept PCA axes of the residual fit
+    idx, pos = [], 0
+    for w, b in zip(plan.widths, plan.bits):
+        if b > 0:
+            idx.extend(range(pos, pos + w))
+        pos += w
+    P, lam = S["V"][:, idx].T, S["lam"][idx]
+    tau = np.sort(want, axis=1)[:, 9]
+    md, ms = saq.estimate_multistage(plan, to_dev(Q), to_dev(packed), to_dev(fac),
+                                     to_dev(tau.astype(np.float32)), 4.0, ref=to_dev(refs[r]))
+    torch.cuda.synchronize()
+    od, os_, _ = oracle.estimate_multistage(Q, M, refs[r], plan.kept_widths, plan.kept_bits,
+                                            e.codes, f64[:, :-1], f64[:, -1], P, lam, 4.0, tau)
+    tol = 2e-5 * scale.max(axis=1)
+    _, lo, _ = oracle.estimate_multistage(Q, M, refs[r], plan.kept_widths, plan.kept_bits,
+                                          e.codes, f64[:, :-1], f64[:, -1], P, lam, 4.0, tau - tol)
+    _, hi, _ = oracle.estimate_multistage(Q, M, refs[r], plan.kept_widths, plan.kept_bits,
+                                          e.codes, f64[:, :-1], f64[:, -1], P, lam, 4.0, tau + tol)
+    ms = ms.cpu().numpy().astype(np.int32)
+    assert np.all((ms >= lo) & (ms <= hi))
+    same = ms == os_
+    assert same.mean() >= 0.999
+    assert np.max(np.abs(md.cpu().numpy() - od)[same] / scale[same]) < 2e-5
