@@ -71,7 +71,7 @@ struct RefRows {
 // (a wave of the last column tile whose second block lies past dk) the wave
 // runs only its first block's MFMAs; the waves of one workgroup may take
 // different variants, which share the same barrier sequence.
-template <int LAYOUT, bool ACC64, bool NORM, int BI, bool FULLB = true>
+template <int LAYOUT, bool ACC64, bool NORM, int BI, bool FULLB, bool REF>
 __device__ __forceinline__ void gemm_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
@@ -95,10 +95,11 @@ __device__ __forceinline__ void gemm_tile_impl(
     // rows past n read row n-1 (always valid memory) and are zeroed on store
     const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
     const float* brow = Mp + int64_t(n0 + br) * k_pad;
-    // this row's reference: the plan's c (zero padded to k_pad) or its row of refs
+    // this row's reference: the plan's c (zero padded to k_pad, shared by
+    // every row) or, with REF, its row of refs
     const float* crow = cp;
     bool ref_bad = false;
-    if (R.refs != nullptr) {
+    if (REF) {
         const int32_t id = R.ids != nullptr ? R.ids[arow_ok ? arow : n - 1] : 0;
         ref_bad = id < 0 || id >= R.K;
         crow = R.refs + int64_t(ref_bad ? 0 : id) * D;
@@ -113,7 +114,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 #pragma unroll
         for (int q = 0; q < ALK / 4; ++q) {
             const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
-            const float4 c4 = *reinterpret_cast<const float4*>(crow + kb + 4 * q);
+            const float4 c4 = *reinterpret_cast<const float4*>((REF ? crow : cp) + kb + 4 * q);
             rx[4 * q + 0] = x4.x; rx[4 * q + 1] = x4.y; rx[4 * q + 2] = x4.z; rx[4 * q + 3] = x4.w;
             rc[4 * q + 0] = c4.x; rc[4 * q + 1] = c4.y; rc[4 * q + 2] = c4.z; rc[4 * q + 3] = c4.w;
         }
@@ -128,7 +129,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 #pragma unroll
         for (int e = 0; e < ALK; ++e) {
             rx[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
-            rc[e] = (kb + e < D) ? crow[kb + e] : 0.f;
+            rc[e] = REF ? ((kb + e < D) ? crow[kb + e] : 0.f) : cp[kb + e];
         }
 #pragma unroll
         for (int e = 0; e < 16; ++e) rb[e] = brow[k0 + bk + e];
@@ -284,7 +285,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 
 // ||x - c||^2 is produced by the first column tile only; the k-loop is
 // specialised so the other tiles carry none of its work.
-template <int LAYOUT, bool ACC64, int BI>
+template <int LAYOUT, bool ACC64, int BI, bool REF = false>
 __device__ __forceinline__ void gemm_tile(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
@@ -293,20 +294,20 @@ __device__ __forceinline__ void gemm_tile(
     // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
     const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
     if (norm2 != nullptr && tile_n == 0)
-        gemm_tile_impl<LAYOUT, ACC64, true, BI>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2,
-                                                tile_m, tile_n, lds, R);
+        gemm_tile_impl<LAYOUT, ACC64, true, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
+                                                           norm2, tile_m, tile_n, lds, R);
     else if (fullb)
-        gemm_tile_impl<LAYOUT, ACC64, false, BI, true>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                       norm2, tile_m, tile_n, lds, R);
+        gemm_tile_impl<LAYOUT, ACC64, false, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
+                                                            norm2, tile_m, tile_n, lds, R);
     else
-        gemm_tile_impl<LAYOUT, ACC64, false, BI, false>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                        norm2, tile_m, tile_n, lds, R);
+        gemm_tile_impl<LAYOUT, ACC64, false, BI, false, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
+                                                             ld, norm2, tile_m, tile_n, lds, R);
 }
 
 // FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
 template <bool ACC64> constexpr int gemm_bi() { return ACC64 ? 1 : 2; }
 
-template <bool VEC, int LAYOUT, bool ACC64>
+template <bool VEC, int LAYOUT, bool ACC64, bool REF>
 __global__ __launch_bounds__(256) void project_kernel(
     const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
     const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
@@ -318,8 +319,8 @@ __global__ __launch_bounds__(256) void project_kernel(
     const int tile_n = local % tiles_n;
     const int tile_m = (local / tiles_n) * NXCD + xcd;
     if (tile_m >= tiles_m) return;
-    gemm_tile<LAYOUT, ACC64, BI>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n,
-                                 lds, R);
+    gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
+                                      tile_n, lds, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -1014,17 +1015,29 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
         return saq::fail(SAQ_EINVAL, "dims-major output needs a 16-byte aligned buffer and ld % 4 == 0");
     if (layout == LAYOUT_TILES && (reinterpret_cast<uintptr_t>(O) & 15) != 0)
         return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
-#define SAQ_LAUNCH_PROJ(V, L, A)                                                                  \
-    hipLaunchKernelGGL((project_kernel<V, L, A>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),   \
+#define SAQ_LAUNCH_PROJ(V, L, A, F)                                                               \
+    hipLaunchKernelGGL((project_kernel<V, L, A, F>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),\
                        p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R)
-#define SAQ_LAUNCH_PROJ2(V, L) \
-    do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true); else SAQ_LAUNCH_PROJ(V, L, false); } while (0)
+#define SAQ_LAUNCH_PROJ2(V, L, F) \
+    do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true, F); else SAQ_LAUNCH_PROJ(V, L, false, F); } while (0)
+    // references per row exist for the tiled (encode) and row (query) layouts
+    const bool ref = R.refs != nullptr;
+    if (ref && layout == LAYOUT_DIMS)
+        return saq::fail(SAQ_EUNSUPPORTED, "per-row references with the dims-major layout");
     if (layout == LAYOUT_TILES) {
-        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_TILES); else SAQ_LAUNCH_PROJ2(false, LAYOUT_TILES);
+        if (ref) {
+            if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_TILES, true); else SAQ_LAUNCH_PROJ2(false, LAYOUT_TILES, true);
+        } else {
+            if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_TILES, false); else SAQ_LAUNCH_PROJ2(false, LAYOUT_TILES, false);
+        }
     } else if (layout == LAYOUT_DIMS) {
-        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_DIMS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_DIMS);
+        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_DIMS, false); else SAQ_LAUNCH_PROJ2(false, LAYOUT_DIMS, false);
     } else {
-        if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_ROWS); else SAQ_LAUNCH_PROJ2(false, LAYOUT_ROWS);
+        if (ref) {
+            if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_ROWS, true); else SAQ_LAUNCH_PROJ2(false, LAYOUT_ROWS, true);
+        } else {
+            if (vec) SAQ_LAUNCH_PROJ2(true, LAYOUT_ROWS, false); else SAQ_LAUNCH_PROJ2(false, LAYOUT_ROWS, false);
+        }
     }
 #undef SAQ_LAUNCH_PROJ2
 #undef SAQ_LAUNCH_PROJ
