@@ -170,3 +170,56 @@ def test_multistage_argument_errors(gauss):
     d2, st = saq.estimate_multistage(plan, empty_q, codes, fac,
                                      torch.empty(0, dtype=torch.float32, device=cuda()), 4.0)
     assert d2.shape == (0, 10) and st.shape == (0, 10)
+
+
+def test_full_size_scans_sampled():
+    """Scans in the benchmark's launch shape: 64 queries against 1,000,000
+    records at D = 768 (the scan leg's dataset shape).  The records are
+    16,384 oracle-encoded records repeated to 1M rows, so every input is the
+    oracle's; every scanned row equals its base record's estimate.  Checked
+    on a sample of 4,000 rows spread over the whole range: the plain scan,
+    the 2-bit prefix scan and the multi-stage scan (m = 4)."""
+    ds = synth.cfg5(2, 1_000_000)
+    base_n, n, nq = 16_384, 1_000_000, 64
+    Xb = ds.rows(0, base_n)
+    mean, _, lam, V = oracle.pca(Xb)
+    plan = saq.Plan.from_basis(mean, V, lam, saq.PlanParams(bits_per_dim=4.0)).upload(0)
+    P, lk = _kept_axes(plan, V, lam)
+    packed, fac, codes = oracle_records(plan, Xb, 4)
+    reps = np.arange(n) % base_n
+    dev_packed = to_dev(packed)[torch.from_numpy(reps).to(cuda())].contiguous()
+    dev_fac = to_dev(fac)[torch.from_numpy(reps).to(cuda())].contiguous()
+    Q = ds.queries(nq)
+    M, c, _ = plan.arrays()
+    f64 = fac.astype(np.float64)
+    plain = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes, f64[:, :-1], f64[:, -1])
+    pre2 = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes, f64[:, :-1], f64[:, -1],
+                           prefix_bits=2)
+    scale = f64[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
+    sample = np.random.default_rng(12).choice(n, 4000, replace=False)
+    sb = reps[sample]
+    say("full-size scans: 64 queries x 1M records, D=768")
+    for label, kw, want in (("plain", {}, plain), ("prefix 2", {"prefix_bits": 2}, pre2)):
+        d2 = saq.estimate_dist(plan, to_dev(Q), dev_packed, dev_fac, **kw)
+        torch.cuda.synchronize()
+        got = d2[:, torch.from_numpy(sample).to(cuda())].cpu().numpy()
+        err = np.max(np.abs(got - want[:, sb]) / scale[:, sb])
+        say(f"  {label}: max err {err:.2e}")
+        assert err < TOL, label
+    tau = np.sort(plain, axis=1)[:, 9]
+    md, ms = saq.estimate_multistage(plan, to_dev(Q), dev_packed, dev_fac,
+                                     to_dev(tau.astype(np.float32)), 4.0)
+    torch.cuda.synchronize()
+    idx = torch.from_numpy(sample).to(cuda())
+    md = md[:, idx].cpu().numpy()
+    ms = ms[:, idx].cpu().numpy().astype(np.int32)
+    S = dict(plan=plan, P=P, lam=lk, packed=packed, fac=fac, codes=codes)
+    ref, rst, _ = _oracle_ms(S, Q, 4.0, tau)
+    tol = TOL * scale.max(axis=1)
+    _, lo, _ = _oracle_ms(S, Q, 4.0, tau - tol)
+    _, hi, _ = _oracle_ms(S, Q, 4.0, tau + tol)
+    assert np.all((ms >= lo[:, sb]) & (ms <= hi[:, sb]))
+    same = ms == rst[:, sb]
+    say(f"  multi-stage: stages identical {same.mean():.6f}")
+    assert same.mean() >= 0.999
+    assert np.max(np.abs(md - ref[:, sb])[same] / scale[:, sb][same]) < TOL
