@@ -676,13 +676,14 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 // is a GEMM between the records' scaled codes a_i = (f_s u_s), one row of
 // D_kept values per record, and the projected queries q'.  A workgroup takes
 // 128 records x 64 queries; a k-step covers 32 kept dims of one segment.
-// Each k-step's raw inputs (16 dims of every bit plane for one record per
-// thread pair, 8 query values per thread, the record's f_s) are fetched one
-// k-step ahead and unpacked into LDS as FP32 f_s (c - (2^B - 1)/2) after the
-// MFMAs of the current k-step; the four waves then run 2 x 16
-// v_mfma_f32_32x32x2_f32 each (wave w: records 32w .. 32w + 31 against all
-// 64 queries).  A segment whose width is not a multiple of 32 pads its last
-// k-step with zeros on both operands.  Segments of at most 8 bits unpack a
+// Each k-step's raw inputs (16 dims of every bit plane of one record per
+// lane, 8 query values per thread, the record's f_s) are fetched one k-step
+// ahead.  After the current k-step's MFMAs each lane unpacks its 16 dims as
+// FP32 f_s (c - (2^B - 1)/2) straight into its own A operand registers
+// (wave w holds records 32w .. 32w + 31), and the queries go to LDS, the
+// only operand the four waves share; each wave then runs 2 x 16
+// v_mfma_f32_32x32x2_f32 against all 64 queries.  A segment whose width is
+// not a multiple of 32 pads its last k-step with zeros on the record side.  Segments of at most 8 bits unpack a
 // plane byte (8 dims) with one lookup in a 256-entry table that spreads its
 // bits to one bit per byte.  With prefix b > 0 a segment reads only its
 // first min(b, B) bit planes, the b-bit prefix floor(c / 2^(B-b)) of every
@@ -701,10 +702,12 @@ constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
 constexpr int EK = 32;                  // kept dims per k-step
 constexpr int ESTR = EK + 4;            // floats per LDS row (conflict-free b128 reads)
-constexpr int EST_LDS_FLOATS = 2 * (ER + EQ) * ESTR;   // 55,296 bytes
+constexpr int EST_LDS_FLOATS = 2 * EQ * ESTR;          // 18,432 bytes: the query slices
 
+// Occupancy: the plain scan fits 4 waves per SIMD without spilling (100
+// VGPRs), the multi-stage variant 3 (its bound state needs about 150).
 template <bool MS>
-__global__ __launch_bounds__(256) void estimate_kernel(
+__global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
@@ -712,8 +715,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(
     float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
     __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
-    float (*As)[ER * ESTR] = reinterpret_cast<float (*)[ER * ESTR]>(lds);
-    float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds + 2 * ER * ESTR);
+    float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds);
     const int t = threadIdx.x;
     {
         uint64_t v = 0;
@@ -728,7 +730,10 @@ __global__ __launch_bounds__(256) void estimate_kernel(
 
     // unpacking: record ur of the tile, dims 16 uh .. 16 uh + 15 of a k-step;
     // records past n read record n - 1 and are never stored
-    const int ur = t >> 1, uh = t & 1;
+    // lane li + 32 lh of wave w unpacks record 32 w + li, dims 16 lh .. 16 lh + 15:
+    // exactly its own A operand of the 32 x 32 x 2 MFMAs (row li, k = 16 lh + j
+    // at step j), so the record tile never passes through LDS
+    const int ur = 32 * wave + li, uh = lh;
     const int64_t ri = min(r0 + ur, n - 1);
     const uint8_t* rec = codes + ri * code_bytes;
     const float* fr = factors + ri * (n_kept + 1);
@@ -738,6 +743,7 @@ __global__ __launch_bounds__(256) void estimate_kernel(
     const float* qrow = Qp + int64_t(qlive ? q0 + qq : 0) * dk;
 
     struct Raw { uint32_t w[16]; float q[8]; float fs; };
+    float Areg[16];     // this lane's A operand of the current k-step
     // bits of a segment the scan reads: all of them, or the first `prefix`
     // (progressive approximation, Section 3.2)
     auto used_bits = [&](int B) { return (prefix > 0 && prefix < B) ? prefix : B; };
@@ -804,10 +810,8 @@ __global__ __launch_bounds__(256) void estimate_kernel(
         float a[16];
 #pragma unroll
         for (int d = 0; d < 16; ++d) a[d] = (d0 + d < W) ? g.fs * (float(c[d]) - h) : 0.f;
-        float* ad = &As[buf][ur * ESTR + 16 * uh];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<float4*>(ad + 4 * q) = make_float4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+        for (int d = 0; d < 16; ++d) Areg[d] = a[d];
         float* bd = &Bs[buf][qq * ESTR + qd];
         *reinterpret_cast<float4*>(bd) = make_float4(g.q[0], g.q[1], g.q[2], g.q[3]);
         *reinterpret_cast<float4*>(bd + 4) = make_float4(g.q[4], g.q[5], g.q[6], g.q[7]);
@@ -880,16 +884,15 @@ __global__ __launch_bounds__(256) void estimate_kernel(
             if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
             const bool more = s1 < n_kept;
             if (more) fetch(g, s1, j1);
-            const float* a0 = &As[buf][(32 * wave + li) * ESTR + lh * 16];
             const float* b0 = &Bs[buf][li * ESTR + lh * 16];
             const float* b1 = b0 + 32 * ESTR;
             float A[16], B0[16], B1[16];
 #pragma unroll
+            for (int d = 0; d < 16; ++d) A[d] = Areg[d];
+#pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float4 va = *reinterpret_cast<const float4*>(a0 + 4 * q);
                 const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
                 const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
-                A[4 * q] = va.x; A[4 * q + 1] = va.y; A[4 * q + 2] = va.z; A[4 * q + 3] = va.w;
                 B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
                 B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
             }
