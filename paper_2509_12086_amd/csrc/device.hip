@@ -753,12 +753,20 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         const int d0 = j0 + 16 * uh;
         const bool any = d0 < W, two = d0 + 8 < W;
         const uint8_t* pl = rec + e.code_off + (d0 >> 3);
+        // both bytes of a lane's 16 dims in one 16-bit load when they are
+        // inside the plane and 2-byte aligned (even record, segment and
+        // plane offsets); otherwise byte loads
+        const bool half = two && ((code_bytes | int64_t(e.code_off) | int64_t(pb)) & 1) == 0;
 #pragma unroll
         for (int p = 0; p < 16; ++p) {
             uint32_t w = 0u;
             if (p < B && any) {
-                w = pl[int64_t(p) * pb];
-                if (two) w |= uint32_t(pl[int64_t(p) * pb + 1]) << 8;
+                if (half) {
+                    w = *reinterpret_cast<const uint16_t*>(pl + int64_t(p) * pb);
+                } else {
+                    w = pl[int64_t(p) * pb];
+                    if (two) w |= uint32_t(pl[int64_t(p) * pb + 1]) << 8;
+                }
             }
             g.w[p] = w;
         }
