@@ -770,10 +770,18 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
             g.w[p] = w;
         }
+        if (qlive && j0 + EK <= W && ((dk | e.col) & 3) == 0) {
+            // whole k-step, 16-byte aligned: two vector loads
+            const float4* q4 = reinterpret_cast<const float4*>(qrow + e.col + j0 + qd);
+            const float4 a4 = q4[0], b4 = q4[1];
+            g.q[0] = a4.x; g.q[1] = a4.y; g.q[2] = a4.z; g.q[3] = a4.w;
+            g.q[4] = b4.x; g.q[5] = b4.y; g.q[6] = b4.z; g.q[7] = b4.w;
+        } else {
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int j = j0 + qd + d;
-            g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
+            for (int d = 0; d < 8; ++d) {
+                const int j = j0 + qd + d;
+                g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
+            }
         }
         // the b-bit prefix estimates with the stored factor times 2^(B - b)
         g.fs = ldexpf(fr[si], e.bits - B);
