@@ -783,8 +783,9 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
                 g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
             }
         }
-        // the b-bit prefix estimates with the stored factor times 2^(B - b)
-        g.fs = ldexpf(fr[si], e.bits - B);
+        // the b-bit prefix estimates with the stored factor times 2^(B - b);
+        // the factor changes only where a segment starts
+        if (j0 == 0) g.fs = ldexpf(fr[si], e.bits - B);
     };
     auto put = [&](const Raw& g, int si, int j0, int buf) {
         const SegEntry e = segs[si];
