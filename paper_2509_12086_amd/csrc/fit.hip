@@ -68,9 +68,10 @@ __device__ __forceinline__ void tile_of(int t, int nt, int& I, int& J) {
 // 32 (w%2) .. +31 of the tile as 2 x 2 blocks of 16 x 16.
 __global__ __launch_bounds__(256) void cov_kernel(const float* __restrict__ X, int64_t n, int D,
                                                   int64_t m, const double* __restrict__ mu,
-                                                  int64_t slice_rows, double* __restrict__ part) {
-    __shared__ double Ya[2][CK * CSTR];
-    __shared__ double Yb[2][CK * CSTR];
+                                                  int64_t slice_rows, int vec,
+                                                  double* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) double Ya[2][CK * CSTR];
+    __shared__ __attribute__((aligned(16))) double Yb[2][CK * CSTR];
     const int nt = (D + CT - 1) / CT;
     int I, J;
     tile_of(blockIdx.x, nt, I, J);
@@ -92,24 +93,41 @@ __global__ __launch_bounds__(256) void cov_kernel(const float* __restrict__ X, i
         mb[e] = (j0 + sc + e < D) ? mu[j0 + sc + e] : 0.0;
     }
     float ra[8], rb[8];
+    // 8 consecutive floats of one row per column block: two 16-byte loads
+    // when rows are 16-byte aligned and the 8 columns are inside D
+    auto load8 = [&](const float* x, int c0, bool live, float (&r)[8]) {
+        if (vec && live && c0 + 8 <= D) {
+            const float4 u = *reinterpret_cast<const float4*>(x + c0);
+            const float4 v = *reinterpret_cast<const float4*>(x + c0 + 4);
+            r[0] = u.x; r[1] = u.y; r[2] = u.z; r[3] = u.w;
+            r[4] = v.x; r[5] = v.y; r[6] = v.z; r[7] = v.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) r[e] = (live && c0 + e < D) ? x[c0 + e] : 0.f;
+        }
+    };
     auto load = [&](int64_t r0) {
         const int64_t r = r0 + sr;
         const bool live = r < r_end;
         const float* x = X + (live ? sample_row(r, n, m) : 0) * int64_t(D);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            ra[e] = (live && i0 + sc + e < D) ? x[i0 + sc + e] : 0.f;
-            rb[e] = (live && j0 + sc + e < D) ? x[j0 + sc + e] : 0.f;
-        }
+        load8(x, i0 + sc, live, ra);
+        load8(x, j0 + sc, live, rb);
     };
     auto store = [&](int64_t r0, int buf) {
         const bool live = r0 + sr < r_end;
+        // x - c in FP64 (exact for FP32 x); rows past the slice and columns
+        // past D are 0 and add nothing.  Stored as pairs (16-byte LDS writes).
+        double2* ya = reinterpret_cast<double2*>(&Ya[buf][sr * CSTR + sc]);
+        double2* yb = reinterpret_cast<double2*>(&Yb[buf][sr * CSTR + sc]);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            // x - c in FP64 (exact for FP32 x); rows past the slice and
-            // columns past D are 0 and add nothing
-            Ya[buf][sr * CSTR + sc + e] = (live && i0 + sc + e < D) ? double(ra[e]) - ma[e] : 0.0;
-            Yb[buf][sr * CSTR + sc + e] = (live && j0 + sc + e < D) ? double(rb[e]) - mb[e] : 0.0;
+        for (int e = 0; e < 8; e += 2) {
+            double2 va, vb;
+            va.x = (live && i0 + sc + e < D) ? double(ra[e]) - ma[e] : 0.0;
+            va.y = (live && i0 + sc + e + 1 < D) ? double(ra[e + 1]) - ma[e + 1] : 0.0;
+            vb.x = (live && j0 + sc + e < D) ? double(rb[e]) - mb[e] : 0.0;
+            vb.y = (live && j0 + sc + e + 1 < D) ? double(rb[e + 1]) - mb[e + 1] : 0.0;
+            ya[e / 2] = va;
+            yb[e / 2] = vb;
         }
     };
 
@@ -220,8 +238,9 @@ saq_status run_covariance(const float* X, int64_t n, int32_t D, int64_t fit_samp
     hipLaunchKernelGGL(mean_reduce_kernel, dim3(cb), dim3(256), 0, st, mpart, S.nb, D, S.m, mu);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e, "mean_reduce_kernel launch");
+    const int vec = (D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     hipLaunchKernelGGL(cov_kernel, dim3(unsigned(S.tiles), unsigned(S.slices)), dim3(256), 0, st, X, n, D,
-                       S.m, mu, S.slice_rows, part);
+                       S.m, mu, S.slice_rows, vec, part);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_err(e, "cov_kernel launch");
     const int64_t el = int64_t(D) * D;
