@@ -706,7 +706,9 @@ constexpr int EST_LDS_FLOATS = 2 * EQ * ESTR;          // 18,432 bytes: the quer
 
 // Occupancy: the plain scan fits 4 waves per SIMD without spilling (100
 // VGPRs), the multi-stage variant 3 (its bound state needs about 150).
-template <bool MS>
+// QB: 32-query MFMA blocks per tile, 2, or 1 when at most 32 queries are
+// scanned (the second block would be all padding).
+template <bool MS, int QB>
 __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
@@ -852,7 +854,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             const int64_t i = rec_of(r);
             on2[r] = i < n ? factors[i * (n_kept + 1) + n_kept] : 0.f;
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < QB; ++bj)
                 if (i < n && q0 + 32 * bj + li < nq) open |= 1u << (16 * bj + r);
         }
     }
@@ -860,7 +862,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // true while any pair of the workgroup is still open
     auto prune = [&](int si) -> bool {
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
+        for (int bj = 0; bj < QB; ++bj) {
             const int q = q0 + 32 * bj + li;
             if (q >= nq) continue;
             const float lb = lbq[int64_t(q) * n_kept + si], th = tau[q];
@@ -909,14 +911,17 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
-                const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
                 B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
-                B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
+                if (QB == 2) {
+                    const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
+                    B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
+                }
             }
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B0[j], acc[0], 0, 0, 0);
-                acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B1[j], acc[1], 0, 0, 0);
+                if (QB == 2)
+                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B1[j], acc[1], 0, 0, 0);
             }
             if (!more) break;
             put(g, s1, j1, buf ^ 1);
@@ -929,7 +934,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // lane: query q0 + 32 bj + li; for register r the record
     // r0 + 32 wave + 8 (r/4) + 4 lh + r%4
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
+    for (int bj = 0; bj < QB; ++bj) {
         const int q = q0 + 32 * bj + li;
         if (q >= nq) continue;
         const float qn = qn2[q];
@@ -1342,9 +1347,14 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
                                   RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
-    hipLaunchKernelGGL(estimate_kernel<false>, grid, dim3(256), 0, st, Qp, nq, std::max(p->D_kept, 1),
-                       qn2, dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
-                       nullptr, nullptr, nullptr, out);
+    if (nq <= 32)
+        hipLaunchKernelGGL((estimate_kernel<false, 1>), grid, dim3(256), 0, st, Qp, nq,
+                           std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
+                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, out);
+    else
+        hipLaunchKernelGGL((estimate_kernel<false, 2>), grid, dim3(256), 0, st, Qp, nq,
+                           std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
+                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
@@ -1387,8 +1397,14 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "stage_bound_kernel launch");
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
-    hipLaunchKernelGGL(estimate_kernel<true>, grid, dim3(256), 0, st, Qp, nq, dk, qn2, dev_seg(p),
-                       p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau, stage, out);
+    if (nq <= 32)
+        hipLaunchKernelGGL((estimate_kernel<true, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau,
+                           stage, out);
+    else
+        hipLaunchKernelGGL((estimate_kernel<true, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau,
+                           stage, out);
     e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }

@@ -201,7 +201,8 @@ def test_estimate_dist(cfg1):
 
 def test_estimate_dist_shapes():
     """The estimate scan's tiles (128 records x 64 queries x 32 dims) on ragged
-    shapes: query counts around 64, record counts around 128, segment widths
+    shapes: query counts around 32 (one query block below it) and 64, record
+    counts around 128, segment widths
     that are not multiples of 32 (down to 3) and 1- to 16-bit segments; the
     result equals the oracle's estimator on the same records (FP32
     accumulation tolerance)."""
@@ -218,7 +219,7 @@ def test_estimate_dist_shapes():
     Xw = (rng.standard_normal((700, D)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3, 0.1],
                                                      [16, 48, 32, 16, 16, 32])).astype(np.float32)
     for plan, Xs in ((p99, X), (pw, Xw)):
-        for n, nq in ((1, 1), (127, 63), (129, 65), (len(Xs), 130)):
+        for n, nq in ((1, 1), (300, 32), (300, 33), (127, 63), (129, 65), (len(Xs), 130)):
             say(f"estimate D={plan.D} n={n} nq={nq}")
             Q = (rng.standard_normal((nq, plan.D)) * Xs.std(0)).astype(np.float32)
             packed, fac, codes = oracle_records(plan, Xs[:n], 4)
