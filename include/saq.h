@@ -150,7 +150,9 @@ void saq_plan_free(saq_plan* plan);
 /* Device-resident copy of the plan: saq_plan_device_bytes() bytes of
    caller-owned device memory, filled by saq_plan_upload (enqueued on stream;
    the host staging copy is kept by the plan until it is freed).  A plan can
-   be uploaded again to another buffer; the last upload is the one used. */
+   be uploaded again to another buffer; the last upload is the one used.
+   Calls that use the plan must run with the upload's device current (the
+   kernels read the buffer there); otherwise they return SAQ_EINVAL. */
 int64_t    saq_plan_device_bytes(const saq_plan* plan);
 saq_status saq_plan_upload(saq_plan* plan, void* dev_buf, void* stream);
 

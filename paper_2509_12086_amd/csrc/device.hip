@@ -1009,7 +1009,18 @@ saq_status hip_fail(hipError_t e, const char* what) {
     return saq::fail(SAQ_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-bool uploaded(const saq_plan* p) { return p && p->dev != nullptr; }
+// The plan must be uploaded, and to the current device: its buffer is read
+// by the kernels launched there.
+saq_status check_plan(const saq_plan* p, const char* what = "plan") {
+    if (!p || p->dev == nullptr) return saq::fail(SAQ_EINVAL, std::string(what) + " not uploaded");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    if (dev != p->dev_id)
+        return saq::fail(SAQ_EINVAL, std::string(what) + " uploaded on device " +
+                                         std::to_string(p->dev_id) + ", current device " +
+                                         std::to_string(dev));
+    return SAQ_OK;
+}
 
 const float* dev_M(const saq_plan* p) {
     return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_M);
@@ -1129,7 +1140,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
     B.any64 = false;
     for (int i = 0; i < count; ++i) {
         const saq_batch_item& it = items[i];
-        if (!uploaded(it.plan)) return saq::fail(SAQ_EINVAL, "batch plan not uploaded");
+        if (saq_status st = check_plan(it.plan, "batch plan"); st != SAQ_OK) return st;
         if (it.n < 0) return saq::fail(SAQ_EINVAL, "negative n");
         if (check_buffers && it.n > 0 && (!it.X_dev || !it.codes_dev || !it.factors_dev))
             return saq::fail(SAQ_EINVAL, "null buffer");
@@ -1227,7 +1238,7 @@ static saq_status check_layout(const saq_plan* p, int64_t n, int64_t ld, int32_t
 
 saq_status saq_project(const saq_plan* p, const float* X, int64_t n, float* O, int64_t ld,
                        int32_t layout, float* norm2, void* stream) {
-    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
     if (n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (n == 0) return SAQ_OK;
     if (saq_status s = check_layout(p, n, ld, layout); s != SAQ_OK) return s;
@@ -1238,7 +1249,7 @@ saq_status saq_project(const saq_plan* p, const float* X, int64_t n, float* O, i
 saq_status saq_quantize(const saq_plan* p, const float* O, int64_t ld, int32_t layout, int64_t n,
                         const float* norm2, int32_t rounds, uint8_t* codes, float* factors,
                         void* stream) {
-    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
     if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (n == 0) return SAQ_OK;
     if (saq_status s = check_layout(p, n, ld, layout); s != SAQ_OK) return s;
@@ -1252,7 +1263,7 @@ saq_status saq_quantize(const saq_plan* p, const float* O, int64_t ld, int32_t l
 static saq_status encode_impl(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
                               uint8_t* codes, float* factors, void* ws, int64_t ws_bytes,
                               void* stream, RefRows R) {
-    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
     if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (n == 0) return SAQ_OK;
     if (!X || !codes || !factors || !ws) return saq::fail(SAQ_EINVAL, "null buffer");
@@ -1333,7 +1344,7 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
                             const uint8_t* codes, const float* factors, int64_t n,
                             int32_t prefix_bits, float* out, void* ws, int64_t ws_bytes,
                             void* stream) {
-    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
     if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (prefix_bits < 0) return saq::fail(SAQ_EINVAL, "prefix_bits < 0");
     if (nq == 0 || n == 0) return SAQ_OK;
@@ -1364,7 +1375,7 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
                                   const uint8_t* codes, const float* factors, int64_t n,
                                   const float* tau, float m, float* out, uint8_t* stage, void* ws,
                                   int64_t ws_bytes, void* stream) {
-    if (!uploaded(p)) return saq::fail(SAQ_EINVAL, "plan not uploaded");
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
     if (nq < 0 || n < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
     if (!(m >= 0.f) || !std::isfinite(m)) return saq::fail(SAQ_EINVAL, "m must be finite and >= 0");
     if (p->S.empty())
