@@ -89,3 +89,28 @@ def test_fit_argument_errors():
         saq.covariance(X, 0, workspace=small)
     with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
         saq.Plan.fit_device(X, saq.PlanParams(), workspace=small)
+
+
+@pytest.mark.parametrize("D", [960, 3072])
+def test_full_size_fit_sample(D):
+    """The benchmark's fit shapes: 65,536 rows at D = 960 (the headline
+    plan's fit rows) and D = 3072, generated on the device; the device moments
+    against the oracle's on the same rows, and at D = 960 the fitted plan
+    against the oracle's plan."""
+    ds = synth.cfg2(65_536) if D == 960 else synth.cfg3(0, 65_536)
+    say(f"full-size fit D={D}: 65,536 rows on the device")
+    Xd = ds.rows_torch(65_536, torch.device("cuda", 0))
+    mean, cov = saq.covariance(Xd, 0)
+    torch.cuda.synchronize()
+    X = Xd.cpu().numpy()
+    c, C, lam, V = oracle.pca(X)
+    err = np.max(np.abs(cov.cpu().numpy() - C)) / np.max(np.abs(C))
+    say(f"  max |cov - oracle| / max|cov| = {err:.2e}")
+    assert np.max(np.abs(mean.cpu().numpy() - c)) <= 1e-12 * np.max(np.abs(X))
+    assert err < 1e-10
+    if D == 960:
+        params = saq.PlanParams(bits_per_dim=4.0, fit_sample=0)
+        p = saq.Plan.fit_device(Xd, params)
+        ref = oracle.plan_search(lam, 4.0, params.granularity, params.max_bits, params.max_width)
+        assert p.widths == ref.widths and p.bits == ref.bits
+        np.testing.assert_allclose(p.arrays()[2], lam, rtol=1e-9, atol=1e-12 * lam[0])

@@ -126,3 +126,34 @@ def test_scans_of_one_list(lists):
     same = ms == os_
     assert same.mean() >= 0.999
     assert np.max(np.abs(md.cpu().numpy() - od)[same] / scale[same]) < 2e-5
+
+
+def test_full_size_reference_encode_sampled():
+    """The benchmark's reference-vector configuration: 1M x 960 rows on the
+    device, each encoded against the nearest of the 1,024 cluster centers (the
+    list centroids), in the launch the benchmark times; 3,000 sampled records
+    against the oracle, which encodes each sampled row with its own
+    centroid."""
+    ds = synth.cfg2()
+    say("reference encode at full size: 1M x 960, 1,024 centroids")
+    X = ds.rows_torch(ds.n, cuda())
+    refs = (ds.centers @ ds.rotation.T).astype(np.float32)
+    rd = torch.from_numpy(refs).to(cuda())
+    rn = (rd.double() ** 2).sum(1)
+    rt = rd.double().T.contiguous()
+    ids = torch.empty(ds.n, dtype=torch.int32, device=cuda())
+    for a in range(0, ds.n, 65536):
+        xb = X[a:a + 65536].double()
+        ids[a:a + xb.shape[0]] = torch.argmin(rn[None, :] - 2.0 * (xb @ rt), dim=1).to(torch.int32)
+    sample = X[:65536].cpu().numpy()
+    R = sample.astype(np.float64) - refs[ids[:65536].cpu().numpy()]
+    _, _, lam, V = oracle.pca(R)
+    plan = saq.Plan.from_basis(np.zeros(ds.d), V, lam, saq.PlanParams(bits_per_dim=4.0)).upload(0)
+    codes, fac = saq.encode(plan, X, 4, refs=rd, ref_ids=ids)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(6).choice(ds.n, 3000, replace=False))
+    it = torch.from_numpy(idx).to(cuda())
+    Xs, ids_s = X[it].cpu().numpy(), ids[it].cpu().numpy()
+    packed, f = codes[it].cpu().numpy(), fac[it].cpu().numpy()
+    del X, codes, fac
+    compare(plan, packed, f, _oracle_by_list(plan, Xs, refs, ids_s), label="reference 1M")
