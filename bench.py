@@ -25,6 +25,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA = 157.3e12     # MI355X dense FP32 matrix FLOP/s
+PEAK_BF16_MFMA = 2.5e15       # MI355X dense bf16 matrix FLOP/s
+SPLIT_PRODUCTS = 6            # bf16 MFMA products per FP32 product in the projection
 PEAK_HBM = 8.0e12             # MI355X HBM3E bytes/s
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix FLOP/s
 VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-ops/s
@@ -186,6 +188,12 @@ def main():
     traffic_workload = f"{n:,} x {D}, {a.bpd:g} b/dim, r={a.rounds}"
     q_valu = recorded_valu("quantize_kernel", traffic_workload)
     proj_tflops = flops / (proj_ms * 1e-3) / 1e12
+    # FP32 accumulation runs the split-operand GEMM: six bf16 products per
+    # FP32 product on the bf16 matrix cores (FP64 totals: FP32 MFMAs)
+    split = not plan.info["projection_fp64_totals"]
+    mfma_flops = flops * (SPLIT_PRODUCTS if split else 1)
+    mfma_peak = PEAK_BF16_MFMA if split else PEAK_FP32_MFMA
+    mfma_tflops = mfma_flops / (proj_ms * 1e-3) / 1e12
     q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
     q_gbs = q_bytes / (quant_ms * 1e-3) / 1e9
     e2e_bytes = n * (4.0 * D + plan.code_bytes + 4.0 * plan.n_factors)
@@ -230,15 +238,20 @@ def main():
             "D_kept": dk, "code_bytes": plan.code_bytes,
         },
         "roofline": {
-            "kernel": "project_kernel (FP32 MFMA GEMM, o = M (x - c))",
+            "kernel": ("project_kernel (o = M (x - c), FP32 products as six bf16 MFMA products "
+                       "of exactly split operands, FP32 accumulation)") if split else
+                      "project_kernel (o = M (x - c), FP32 MFMAs, FP64 k-tile totals)",
             "bound": "mfma",
-            "achieved": proj_tflops,
-            "peak": PEAK_FP32_MFMA / 1e12,
+            "achieved": mfma_tflops,
+            "peak": mfma_peak / 1e12,
             "unit": "TFLOP/s",
-            "frac": proj_tflops * 1e12 / PEAK_FP32_MFMA,
+            "frac": mfma_tflops * 1e12 / mfma_peak,
             "traffic": recorded_traffic("project_kernel", traffic_workload),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-            "algorithmic_per_launch": flops,
+            "algorithmic_per_launch": mfma_flops,
+            "fp32_flops_per_launch": flops,
+            "fp32_equivalent_tflops": proj_tflops,
+            "fp32_mfma_peak_tflops": PEAK_FP32_MFMA / 1e12,
             "algorithmic_bytes_per_launch": proj_bytes,
             "avg_ms": proj_ms,
         },
@@ -258,7 +271,7 @@ def main():
             "bytes_per_vector": e2e_bytes / n,
             "hbm_frac": e2e_bytes / (ms_step * 1e-3) / PEAK_HBM,
             "binding_roofline_vectors_per_s": min(PEAK_HBM / (e2e_bytes / n),
-                                                  PEAK_FP32_MFMA / (2.0 * D * dk)),
+                                                  mfma_peak / (mfma_flops / n)),
         },
         "cpu_baseline": cpu,
         "fit": fit,

@@ -64,8 +64,11 @@ typedef struct {
     int64_t  fit_sample;      /* rows used for mean/covariance (0 = all); an evenly spaced subset */
     uint64_t seed;            /* seeds the per-segment rotations */
     int32_t  projection_accumulation; /* 0 auto: FP64 k-tile totals when D > 1024 or a kept
-                                         segment has >= 8 bits, else FP32; 1: FP32 throughout;
-                                         2: FP32 per 32-wide k-tile, FP64 across tiles */
+                                         segment has >= 8 bits, else FP32; 1: FP32 throughout
+                                         (each FP32 product formed as six bf16 matrix-core
+                                         products of exactly split operands, error below one
+                                         FP32 rounding); 2: FP32 MFMAs per 32-wide k-tile,
+                                         FP64 across tiles */
 } saq_plan_params;
 
 typedef struct {
@@ -156,12 +159,13 @@ void saq_plan_free(saq_plan* plan);
 int64_t    saq_plan_device_bytes(const saq_plan* plan);
 saq_status saq_plan_upload(saq_plan* plan, void* dev_buf, void* stream);
 
-/* Encode n rows X_dev [n x D] (row-major FP32, device): o = M (x - c) with an
-   FP32 matrix-core GEMM (Eq. rotate), then for every kept segment the grid
-   quantization of Eq. (find_nearest_code) and `rounds` rounds of the code
-   adjustment of Algorithm 1 (stopping early once a round changes nothing,
-   which cannot alter the result), then the stored factors and the bit-plane
-   record.  codes_dev [n x code_bytes], factors_dev [n x n_factors].
+/* Encode n rows X_dev [n x D] (row-major FP32, device): o = M (x - c) with a
+   matrix-core GEMM at FP32 accuracy (Eq. rotate; the plan's
+   projection_accumulation picks FP32 or FP64-total accumulation), then for
+   every kept segment the grid quantization of Eq. (find_nearest_code) and
+   `rounds` rounds of the code adjustment of Algorithm 1 (stopping early once
+   a round changes nothing, which cannot alter the result), then the stored
+   factors and the bit-plane record.  codes_dev [n x code_bytes], factors_dev [n x n_factors].
    ws_dev: saq_encode_workspace_bytes(plan, n) bytes of device scratch.
    A kept segment wider than the quantize kernel's LDS code buffer (1024 dims
    at <= 8 bits, 512 dims above) gives SAQ_EUNSUPPORTED. */

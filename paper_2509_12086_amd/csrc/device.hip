@@ -1,9 +1,12 @@
 // Device half of libsaq.so (gfx950): the SAQ encode hot path and the
 // estimate scan, plus their C-ABI entry points.
 //
-//   project_kernel   o = M (x - c) as an FP32 matrix-core GEMM
-//                    (v_mfma_f32_32x32x2_f32), centering fused into the
-//                    A-tile load, exact FP64 ||x - c||^2 on the side.
+//   project_kernel   o = M (x - c) as a matrix-core GEMM with FP32
+//                    accumulation: FP32 products formed exactly from split
+//                    bf16 operands (v_mfma_f32_32x32x16_bf16), or FP32
+//                    MFMAs (v_mfma_f32_32x32x2_f32) with FP64 k-tile totals;
+//                    centering fused into the A-tile load, exact FP64
+//                    ||x - c||^2 on the side.
 //   quantize_kernel  per (vector, kept segment): v_max, the grid code of
 //                    Eq. (find_nearest_code), the code adjustment of
 //                    Algorithm 1 with FP64 decisions, the factor and the
@@ -25,6 +28,9 @@
 using saq::SegEntry;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -36,21 +42,20 @@ constexpr int NXCD = 8;               // MI355X: 8 XCDs, workgroups dealt round-
 enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1, LAYOUT_TILES = 2 };
 
 // ---------------------------------------------------------------------------
-// Projection GEMM.  Workgroup = 256 threads (4 waves) computes a 128 x 128
-// tile of O (vectors x kept dims); each wave a 64 x 64 quarter as 2 x 2
-// 32x32 MFMA blocks.  The 32-wide k-step is split between the two half-waves:
-// half h feeds k = 16h + j at MFMA step j, so every lane reads 16 contiguous
-// floats per row from LDS (4 x ds_read_b128).
+// Projection GEMM, FP32-MFMA form.  Workgroup = 256 threads (4 waves)
+// computes a (64 BI) x 128 tile of O (vectors x kept dims); each wave a
+// (32 BI) x 64 part as BI x 2 32x32 MFMA blocks.  The 32-wide k-step is split
+// between the two half-waves: half h feeds k = 16h + j at MFMA step j, so
+// every lane reads 16 contiguous floats per row from LDS (4 x ds_read_b128).
 //
 // Tile order is XCD-aware: workgroup b runs on XCD b % 8; XCD x walks row
 // tiles x, x+8, ... and, inside each, all column tiles back to back, so the
 // X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
 // ---------------------------------------------------------------------------
-// BI = 32-row MFMA blocks per wave along the vectors: the workgroup tile is
-// (64 BI) vectors x 128 kept dims.  BI = 2 (FP32 accumulation): 128 x 128,
-// 73.7 KB of LDS, two workgroups per compute unit.  BI = 1 (FP64 k-tile
-// totals, which hold 64 doubles per 32 x 32 block and lane pair): 64 x 128,
-// 55.3 KB, so the totals fit two workgroups per compute unit as well.
+// BI = 32-row MFMA blocks per wave along the vectors.  The projection takes
+// this form only with FP64 k-tile totals (64 doubles per 32 x 32 block and
+// lane pair), at BI = 1: 64 x 128 tiles, 55.3 KB of LDS, two workgroups per
+// compute unit.  FP32 accumulation runs the split-operand GEMM below.
 template <int BI> constexpr int gemm_rows() { return 64 * BI; }
 template <int BI> constexpr int gemm_lds_floats() { return 2 * (64 * BI + TN) * LDS_STRIDE; }
 
@@ -66,6 +71,35 @@ struct RefRows {
     const int32_t* ids;
     int32_t K;
 };
+
+// Stores rows row .. row+3 of column col of O in the output layout.
+template <int LAYOUT>
+__device__ __forceinline__ void store_quad(float* __restrict__ O, int64_t ld, int64_t n, int64_t row,
+                                           int col, float v0, float v1, float v2, float v3) {
+    if (LAYOUT == LAYOUT_TILES) {
+        // whole 64-row tiles: rows of the last tile past n (copies of row
+        // n-1) are stored too
+        if (row < ((n + 63) & ~int64_t(63))) {
+            float* dst = O + ((row >> 6) * ld + col) * 64 + (row & 63);
+            *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+        }
+    } else if (LAYOUT == LAYOUT_DIMS) {
+        float* dst = O + int64_t(col) * ld + row;
+        if (row + 3 < n) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
+        } else {
+            if (row + 0 < n) dst[0] = v0;
+            if (row + 1 < n) dst[1] = v1;
+            if (row + 2 < n) dst[2] = v2;
+            if (row + 3 < n) dst[3] = v3;
+        }
+    } else {
+        if (row + 0 < n) O[(row + 0) * ld + col] = v0;
+        if (row + 1 < n) O[(row + 1) * ld + col] = v1;
+        if (row + 2 < n) O[(row + 2) * ld + col] = v2;
+        if (row + 3 < n) O[(row + 3) * ld + col] = v3;
+    }
+}
 
 // FULLB: both of the wave's 32-column blocks hold kept dims.  Without it
 // (a wave of the last column tile whose second block lies past dk) the wave
@@ -256,70 +290,283 @@ __device__ __forceinline__ void gemm_tile_impl(
                     v0 = acc[bi][bj][4 * g + 0]; v1 = acc[bi][bj][4 * g + 1];
                     v2 = acc[bi][bj][4 * g + 2]; v3 = acc[bi][bj][4 * g + 3];
                 }
-                if (LAYOUT == LAYOUT_TILES) {
-                    // whole 64-row tiles: rows of the last tile past n (copies
-                    // of row n-1) are stored too
-                    if (row < ((n + 63) & ~int64_t(63))) {
-                        float* dst = O + ((row >> 6) * ld + col) * 64 + (row & 63);
-                        *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
-                    }
-                } else if (LAYOUT == LAYOUT_DIMS) {
-                    float* dst = O + int64_t(col) * ld + row;
-                    if (row + 3 < n) {
-                        *reinterpret_cast<float4*>(dst) = make_float4(v0, v1, v2, v3);
-                    } else {
-                        if (row + 0 < n) dst[0] = v0;
-                        if (row + 1 < n) dst[1] = v1;
-                        if (row + 2 < n) dst[2] = v2;
-                        if (row + 3 < n) dst[3] = v3;
-                    }
-                } else {
-                    if (row + 0 < n) O[(row + 0) * ld + col] = v0;
-                    if (row + 1 < n) O[(row + 1) * ld + col] = v1;
-                    if (row + 2 < n) O[(row + 2) * ld + col] = v2;
-                    if (row + 3 < n) O[(row + 3) * ld + col] = v3;
-                }
+                store_quad<LAYOUT>(O, ld, n, row, col, v0, v1, v2, v3);
             }
         }
 }
 
-// ||x - c||^2 is produced by the first column tile only; the k-loop is
-// specialised so the other tiles carry none of its work.
+
+// ---------------------------------------------------------------------------
+// Split-operand projection (FP32 accumulation).  Every FP32 operand a is
+// written exactly as a0 + a1 + a2 in bf16 (RNE to 8 significant bits, then
+// RNE of the exact remainder, twice), and a b as the six products a_i b_j
+// with i + j <= 2, the bf16x6 scheme of Henry, Tang and Heinecke (2019).  The
+// three dropped products are below 2^-24 |a b| together, the size of one FP32
+// rounding, and the MFMAs (v_mfma_f32_32x32x16_bf16) accumulate in FP32, so
+// o keeps FP32 accuracy; the bf16 matrix rate is 16x the FP32 one, so the six
+// products take 3/8 of the FP32 MFMA time.
+//
+// Tile (64 BI) x 128, k-step 16, four waves of (32 BI) x 64 (BI x 2 blocks
+// of 32 x 32); BI = 2 for the plain launches, 1 in grouped launches that
+// also carry FP64-total datasets.  Every output element sees the same MFMA
+// sequence over k in both shapes, so they give identical results.  Per
+// buffer, LDS holds both operands as 16-byte chunks [A|B][term][k half]
+// [row]: a lane's MFMA operand (8 bf16 of one row, k half = lane / 32) is one
+// chunk, and a wave reads two contiguous 512-byte runs.  The X rows are split
+// as they are staged, thread t taking row t % (64 BI) and k half
+// t / (64 BI), so a wave writes 64 consecutive chunks; M comes pre-split
+// from the plan in the same chunk order, one 16-byte copy per chunk.  A
+// k-step has only 24 MFMAs per wave (768 cycles), too short to cover a
+// global load, so X and the B chunks are loaded two k-steps ahead into
+// alternating register sets.  For BI = 2, 48 KB of LDS and at most 168 VGPRs
+// give three workgroups per compute unit (two with per-row references,
+// whose extra c registers would spill at three).
+// ---------------------------------------------------------------------------
+constexpr int SK = saq::kSplitK;              // input dims per k-step
+constexpr int SCB = saq::kSplitChunks;        // B chunks per buffer
+template <int BI> constexpr int split_lds_floats() { return 2 * (6 * 64 * BI + SCB) * 4; }
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const bf16x2 v = {static_cast<__bf16>(a), static_cast<__bf16>(b)};
+    return __builtin_bit_cast(uint32_t, v);
+}
+// (a, b) -> three packed bf16 pairs, a = a0 + a1 + a2 exactly (normal a)
+__device__ __forceinline__ void split3(float a, float b, uint32_t& h0, uint32_t& h1, uint32_t& h2) {
+    h0 = pack_bf16x2(a, b);
+    const float ra = a - __uint_as_float(h0 << 16), rb = b - __uint_as_float(h0 & 0xffff0000u);
+    h1 = pack_bf16x2(ra, rb);
+    h2 = pack_bf16x2(ra - __uint_as_float(h1 << 16), rb - __uint_as_float(h1 & 0xffff0000u));
+}
+__device__ __forceinline__ floatx16 mfma_bf16(u32x4 a, u32x4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// lds: split_lds_floats<BI>() floats, free on entry; on return free except
+// after a NORM tile (the norm hand-off leaves a barrier-protected write).
+template <int LAYOUT, bool NORM, int BI, bool FULLB, bool REF>
+__device__ __forceinline__ void gemm_split_tile_impl(
+    bool vec, const float* __restrict__ X, int64_t n, int D, const u32x4* __restrict__ Ms,
+    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
+    static_assert(BI == 1 || BI == 2, "tile shapes: 64 x 128 or 128 x 128");
+    constexpr int RM = 64 * BI;                 // vectors per tile
+    constexpr int SCA = 6 * RM;                 // A chunks per buffer
+    constexpr int SCH = SCA + SCB;              // chunks per buffer
+    u32x4* L = reinterpret_cast<u32x4*>(lds);
+    const int64_t m0 = int64_t(tile_m) * RM;
+    const int n0 = tile_n * TN;
+    const int ksteps = k_pad / SK;
+
+    const int t = threadIdx.x;
+    const bool stager = t < 2 * RM;     // threads that stage A
+    const int lr = t % RM;              // A row staged by this thread
+    // its k half of the step, the same for the whole wave: the plan's c is
+    // read with scalar loads
+    const int kh = __builtin_amdgcn_readfirstlane((t / RM) & 1);
+    const int64_t arow = m0 + lr;
+    const bool arow_ok = arow < n;
+    // rows past n read row n-1 (always valid memory); their outputs and
+    // norms are never stored
+    const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
+    // this thread copies B chunks t, t + 256, t + 512 of every k-step
+    const u32x4* msrc = Ms + int64_t(tile_n) * ksteps * SCB + t;
+    const float* crow = cp;
+    bool ref_bad = false;
+    if (REF) {
+        const int32_t id = R.ids != nullptr ? R.ids[arow_ok ? arow : n - 1] : 0;
+        ref_bad = id < 0 || id >= R.K;
+        crow = R.refs + int64_t(ref_bad ? 0 : id) * D;
+    }
+    double nacc = 0.0;
+
+    // raw global values, loaded two k-steps ahead into alternating register
+    // sets: X (and, with per-row references, c) and the B chunks
+    struct Stage { float x[8]; float c[8]; u32x4 b[3]; };
+    Stage sA, sB;
+    const int kfull = vec ? (D / SK) : 0;
+    auto load_stage = [&](int kt, Stage& g) {
+        if (stager) {
+            const int kb = kt * SK + 8 * kh;
+            if (kt < kfull) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
+                    g.x[4 * q + 0] = x4.x; g.x[4 * q + 1] = x4.y; g.x[4 * q + 2] = x4.z; g.x[4 * q + 3] = x4.w;
+                    if (REF) {
+                        const float4 c4 = *reinterpret_cast<const float4*>(crow + kb + 4 * q);
+                        g.c[4 * q + 0] = c4.x; g.c[4 * q + 1] = c4.y;
+                        g.c[4 * q + 2] = c4.z; g.c[4 * q + 3] = c4.w;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    g.x[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
+                    if (REF) g.c[e] = (kb + e < D) ? crow[kb + e] : 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 3; ++p) g.b[p] = msrc[int64_t(kt) * SCB + 256 * p];
+    };
+    auto store_step = [&](int kt, int buf, const Stage& g) {
+        if (stager) {
+            const int kb = kt * SK + 8 * kh;
+            float ra[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                // the plan's c is zero padded to k_pad: one uniform address
+                const float c = REF ? g.c[e] : cp[kb + e];
+                ra[e] = g.x[e] - c;
+                if (NORM) {
+                    // exact (x - c)^2 in FP64; padding entries are 0 - 0
+                    const double d = double(g.x[e]) - double(c);
+                    nacc = fma(d, d, nacc);
+                }
+            }
+            uint32_t a0[4], a1[4], a2[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) split3(ra[2 * q], ra[2 * q + 1], a0[q], a1[q], a2[q]);
+            u32x4* A = L + buf * SCH + kh * RM + lr;
+            A[0] = u32x4{a0[0], a0[1], a0[2], a0[3]};
+            A[2 * RM] = u32x4{a1[0], a1[1], a1[2], a1[3]};
+            A[4 * RM] = u32x4{a2[0], a2[1], a2[2], a2[3]};
+        }
+        u32x4* B = L + buf * SCH + SCA + t;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) B[256 * p] = g.b[p];
+    };
+
+    const int wave = t >> 6, lane = t & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 31, lh = lane >> 5;
+    floatx16 acc[BI][2];
+#pragma unroll
+    for (int i = 0; i < BI; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    auto kstep = [&](int kt, const Stage& cur, Stage& nxt) {
+        const int buf = kt & 1;
+        if (kt + 2 < ksteps) load_stage(kt + 2, nxt);
+        const u32x4* Ar = L + buf * SCH + lh * RM + wm * (32 * BI) + li;
+        const u32x4* Br = L + buf * SCH + SCA + lh * TN + wn * 64 + li;
+        u32x4 a[BI][3], b[2][3];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int i = 0; i < BI; ++i) a[i][p] = Ar[2 * RM * p + 32 * i];
+            b[0][p] = Br[2 * TN * p];
+            if (FULLB) b[1][p] = Br[2 * TN * p + 32];
+        }
+        // the six products, smallest terms first
+        constexpr int TA[6] = {2, 1, 0, 1, 0, 0};
+        constexpr int TB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+            for (int i = 0; i < BI; ++i) {
+                acc[i][0] = mfma_bf16(a[i][TA[u]], b[0][TB[u]], acc[i][0]);
+                if (FULLB) acc[i][1] = mfma_bf16(a[i][TA[u]], b[1][TB[u]], acc[i][1]);
+            }
+        if (kt + 1 < ksteps) store_step(kt + 1, buf ^ 1, cur);
+        __syncthreads();
+    };
+    load_stage(0, sA);
+    store_step(0, 0, sA);
+    load_stage(1, sB);              // k_pad is a multiple of 32: ksteps >= 2, even
+    __syncthreads();
+    for (int kt = 0; kt < ksteps; kt += 2) {
+        kstep(kt, sB, sA);
+        kstep(kt + 1, sA, sB);
+    }
+
+    if (NORM) {
+        // the row's second half-sum comes from thread t + RM through LDS
+        // (free after the last k-step's barrier)
+        double* hand = reinterpret_cast<double*>(lds);
+        if (stager && kh == 1) hand[lr] = nacc;
+        __syncthreads();
+        if (stager && kh == 0 && arow_ok)
+            norm2[arow] = ref_bad ? __builtin_nanf("") : float(nacc + hand[lr]);
+    }
+    // epilogue: lane holds column n0 + wn*64 + 32*bj + li and, for register
+    // r, row m0 + wm*32*BI + 32*bi + 8*(r/4) + 4*lh + r%4
+#pragma unroll
+    for (int bi = 0; bi < BI; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = n0 + wn * 64 + bj * 32 + li;
+            if (col >= dk) continue;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t row = m0 + wm * (32 * BI) + bi * 32 + 8 * g + 4 * lh;
+                store_quad<LAYOUT>(O, ld, n, row, col, acc[bi][bj][4 * g + 0], acc[bi][bj][4 * g + 1],
+                                   acc[bi][bj][4 * g + 2], acc[bi][bj][4 * g + 3]);
+            }
+        }
+}
+
+// One output tile: FP32 accumulation runs the split-operand GEMM, FP64
+// k-tile totals the FP32 MFMAs.  ||x - c||^2 is produced by the first column
+// tile only; the k-loop is specialised so the other tiles carry none of its
+// work.
 template <int LAYOUT, bool ACC64, int BI, bool REF = false>
 __device__ __forceinline__ void gemm_tile(
     bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
-    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
+    const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
+    float* __restrict__ O, int64_t ld, float* __restrict__ norm2, int tile_m, int tile_n,
+    float* __restrict__ lds, RefRows R) {
     // the wave's second 32-column block (wave w covers columns
     // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
     const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
-    if (norm2 != nullptr && tile_n == 0)
-        gemm_tile_impl<LAYOUT, ACC64, true, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                           norm2, tile_m, tile_n, lds, R);
-    else if (fullb)
-        gemm_tile_impl<LAYOUT, ACC64, false, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O, ld,
-                                                            norm2, tile_m, tile_n, lds, R);
-    else
-        gemm_tile_impl<LAYOUT, ACC64, false, BI, false, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
-                                                             ld, norm2, tile_m, tile_n, lds, R);
+    if constexpr (!ACC64) {
+        if (norm2 != nullptr && tile_n == 0)
+            gemm_split_tile_impl<LAYOUT, true, BI, true, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
+                                                              ld, norm2, tile_m, tile_n, lds, R);
+        else if (fullb)
+            gemm_split_tile_impl<LAYOUT, false, BI, true, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
+                                                               ld, norm2, tile_m, tile_n, lds, R);
+        else
+            gemm_split_tile_impl<LAYOUT, false, BI, false, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
+                                                                ld, norm2, tile_m, tile_n, lds, R);
+    } else {
+        if (norm2 != nullptr && tile_n == 0)
+            gemm_tile_impl<LAYOUT, true, true, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
+                                                              ld, norm2, tile_m, tile_n, lds, R);
+        else if (fullb)
+            gemm_tile_impl<LAYOUT, true, false, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
+                                                               ld, norm2, tile_m, tile_n, lds, R);
+        else
+            gemm_tile_impl<LAYOUT, true, false, BI, false, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
+                                                                ld, norm2, tile_m, tile_n, lds, R);
+    }
 }
 
-// FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
+// FP32 accumulation runs the 128 x 128 split-operand tile, FP64 k-tile
+// totals the 64 x 128 FP32-MFMA tile
 template <bool ACC64> constexpr int gemm_bi() { return ACC64 ? 1 : 2; }
+template <bool ACC64> constexpr int gemm_lds_size() {
+    return ACC64 ? gemm_lds_floats<1>() : split_lds_floats<2>();
+}
 
 template <bool VEC, int LAYOUT, bool ACC64, bool REF>
-__global__ __launch_bounds__(256) void project_kernel(
-    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp, int k_pad,
-    const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tiles_m, int tiles_n, RefRows R) {
+__global__ __launch_bounds__(256, ACC64 ? 1 : (REF ? 2 : 3)) void project_kernel(
+    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
+    const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
+    float* __restrict__ O, int64_t ld, float* __restrict__ norm2, int tiles_m, int tiles_n,
+    RefRows R) {
     constexpr int BI = gemm_bi<ACC64>();
-    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_floats<BI>()];
+    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_size<ACC64>()];
     const int bid = blockIdx.x;
     const int xcd = bid % NXCD, local = bid / NXCD;
     const int tile_n = local % tiles_n;
     const int tile_m = (local / tiles_n) * NXCD + xcd;
     if (tile_m >= tiles_m) return;
-    gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Mp, k_pad, cp, dk, O, ld, norm2, tile_m,
+    gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Mp, Ms, k_pad, cp, dk, O, ld, norm2, tile_m,
                                       tile_n, lds, R);
 }
 
@@ -606,16 +853,16 @@ constexpr int BATCH_MAX = 16;
 
 struct GemmSet {
     const float* X; int64_t n; int D; int vec; int acc64;
-    const float* Mp; int k_pad; const float* cp; int dk; int tiles_m; int tiles_n;
+    const float* Mp; const u32x4* Ms; int k_pad; const float* cp; int dk; int tiles_m; int tiles_n;
     float* O; int64_t ld; float* norm2;
     int64_t first_block;
 };
 struct GemmArgs { GemmSet set[BATCH_MAX]; int count; int xcd_order; };
 
 template <bool ACC64>
-__global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) {
+__global__ __launch_bounds__(256, ACC64 ? 1 : 3) void grouped_gemm_kernel(const GemmArgs args) {
     constexpr int BI = gemm_bi<ACC64>();
-    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_floats<BI>()];
+    __shared__ __attribute__((aligned(16))) float lds[gemm_lds_size<ACC64>()];
     const int64_t b = blockIdx.x;
     int d = 0;
     while (d + 1 < args.count && b >= args.set[d + 1].first_block) ++d;
@@ -637,11 +884,11 @@ __global__ __launch_bounds__(256) void grouped_gemm_kernel(const GemmArgs args) 
     // one tile shape per launch: in a launch with FP64 totals, datasets
     // without them accumulate in FP32 on the same tile
     if (S.acc64)
-        gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
+        gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.Ms, S.k_pad, S.cp, S.dk,
                                           S.O, S.ld, S.norm2, tile_m, tile_n, lds,
                                           RefRows{nullptr, nullptr, 0});
     else
-        gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.k_pad, S.cp, S.dk,
+        gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.Ms, S.k_pad, S.cp, S.dk,
                                           S.O, S.ld, S.norm2, tile_m, tile_n, lds,
                                           RefRows{nullptr, nullptr, 0});
 }
@@ -1022,6 +1269,9 @@ saq_status check_plan(const saq_plan* p, const char* what = "plan") {
     return SAQ_OK;
 }
 
+const u32x4* dev_Ms(const saq_plan* p) {
+    return reinterpret_cast<const u32x4*>(static_cast<const char*>(p->dev) + p->layout.off_Ms);
+}
 const float* dev_M(const saq_plan* p) {
     return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_M);
 }
@@ -1053,7 +1303,8 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
         return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
 #define SAQ_LAUNCH_PROJ(V, L, A, F)                                                               \
     hipLaunchKernelGGL((project_kernel<V, L, A, F>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),\
-                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R)
+                       dev_Ms(p), p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m,  \
+                       tiles_n, R)
 #define SAQ_LAUNCH_PROJ2(V, L, F) \
     do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true, F); else SAQ_LAUNCH_PROJ(V, L, false, F); } while (0)
     // references per row exist for the tiled (encode) and row (query) layouts
@@ -1179,7 +1430,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         GemmSet& G = B.g.set[B.g.count++];
         G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
         G.vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
-        G.Mp = dev_M(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
+        G.Mp = dev_M(p); G.Ms = dev_Ms(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
         const int rows = B.any64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
         G.tiles_m = int((it.n + rows - 1) / rows); G.tiles_n = p->layout.n_pad / TN;
         G.O = O; G.ld = ld; G.norm2 = nrm;

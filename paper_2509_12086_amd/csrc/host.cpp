@@ -34,11 +34,28 @@ DeviceLayout device_layout(const saq_plan& p) {
     L.n_pad = std::max(kGemmTileN, (p.D_kept + kGemmTileN - 1) / kGemmTileN * kGemmTileN);
     L.k_pad = (p.D + kGemmTileK - 1) / kGemmTileK * kGemmTileK;
     L.off_M = 0;
-    L.off_c = align256(L.off_M + int64_t(L.n_pad) * L.k_pad * 4);
+    L.off_Ms = align256(L.off_M + int64_t(L.n_pad) * L.k_pad * 4);
+    const int64_t split_chunks = int64_t(L.n_pad / kGemmTileN) * (L.k_pad / kSplitK) * kSplitChunks;
+    L.off_c = align256(L.off_Ms + split_chunks * 16);
     L.off_seg = align256(L.off_c + int64_t(L.k_pad) * 4);
     L.off_S = align256(L.off_seg + int64_t(std::max(p.n_kept, 1)) * int64_t(sizeof(SegEntry)));
     L.bytes = align256(L.off_S + int64_t(std::max<size_t>(p.S.size(), 1)) * 4);
     return L;
+}
+
+// bf16 with round-to-nearest-even of a finite FP32 value (its upper 16 bits
+// after rounding), and the FP32 value of a bf16
+static uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+static float bf16_value(uint16_t h) {
+    const uint32_t u = uint32_t(h) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
 }
 
 void build_staging(saq_plan& p) {
@@ -48,6 +65,23 @@ void build_staging(saq_plan& p) {
     float* M = reinterpret_cast<float*>(p.staging.data() + L.off_M);
     for (int32_t r = 0; r < p.D_kept; ++r)
         std::memcpy(M + int64_t(r) * L.k_pad, p.M.data() + int64_t(r) * p.D, size_t(p.D) * 4);
+    // M_split: each entry as three bf16 terms, in the GEMM's chunk order
+    uint16_t* Ms = reinterpret_cast<uint16_t*>(p.staging.data() + L.off_Ms);
+    const int ksteps = L.k_pad / kSplitK;
+    for (int tile = 0; tile < L.n_pad / kGemmTileN; ++tile)
+        for (int ks = 0; ks < ksteps; ++ks)
+            for (int half = 0; half < 2; ++half)
+                for (int row = 0; row < kGemmTileN; ++row)
+                    for (int e = 0; e < 8; ++e) {
+                        float v = M[int64_t(tile * kGemmTileN + row) * L.k_pad + ks * kSplitK + 8 * half + e];
+                        for (int term = 0; term < 3; ++term) {
+                            const uint16_t h = bf16_rne(v);
+                            const int64_t chunk = (int64_t(tile) * ksteps + ks) * kSplitChunks +
+                                                  term * 2 * kGemmTileN + half * kGemmTileN + row;
+                            Ms[chunk * 8 + e] = h;
+                            v -= bf16_value(h);          // exact: the remainder fits in FP32
+                        }
+                    }
     float* c = reinterpret_cast<float*>(p.staging.data() + L.off_c);
     std::memcpy(c, p.c.data(), size_t(p.D) * 4);
     std::memcpy(p.staging.data() + L.off_seg, p.kept.data(), p.kept.size() * sizeof(SegEntry));

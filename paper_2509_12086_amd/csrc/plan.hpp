@@ -12,6 +12,11 @@ namespace saq {
 
 // Device plan layout (one caller-owned buffer, every region 256-byte aligned):
 //   M_pad   float [n_pad x k_pad]   rows = kept dims in plan order, zero padded
+//   M_split 16-byte chunks [n_pad/128][k_pad/16][3][2][128]: M_pad written as
+//           three bf16 terms per entry (m = m0 + m1 + m2, each the RNE bf16 of
+//           what the previous terms leave), chunk (tile, step, term, half, row)
+//           holding entries k = 16 step + 8 half .. + 7 of row 128 tile + row,
+//           the order the split-operand GEMM stages them in LDS
 //   c_pad   float [k_pad]
 //   segtab  int32 [n_kept x 4]      column start, width, bits, code byte offset
 //   S       float [sum_s W_s^2]     per kept segment, row-major W x W blocks
@@ -19,6 +24,8 @@ namespace saq {
 constexpr int kGemmTileN = 128;   // GEMM tile along the kept dims
 constexpr int kGemmTileK = 32;    // GEMM tile along the input dims
 constexpr int kGemmTileM = 128;   // GEMM tile along the vectors
+constexpr int kSplitK = 16;       // k-step of the split-operand GEMM
+constexpr int kSplitChunks = 3 * 2 * kGemmTileN;   // 16-byte chunks per tile and k-step
 
 struct SegEntry {
     int32_t col;      // first kept column
@@ -29,7 +36,7 @@ struct SegEntry {
 
 struct DeviceLayout {
     int32_t n_pad = 0, k_pad = 0;
-    int64_t off_M = 0, off_c = 0, off_seg = 0, off_S = 0, bytes = 0;
+    int64_t off_M = 0, off_Ms = 0, off_c = 0, off_seg = 0, off_S = 0, bytes = 0;
 };
 
 }  // namespace saq

@@ -1,0 +1,63 @@
+"""The pre-split projection matrix the split-operand GEMM reads.
+
+With FP32 accumulation the projection forms each FP32 product from operands
+written exactly as three bf16 terms.  The plan builds M's terms on the host
+and uploads them beside M.  Read back from the device buffer, the terms of
+every entry must sum to the FP32 entry exactly, and each term must be the
+round-to-nearest-even bf16 of what the earlier terms leave (so the first
+term is within 2^-8 and the first two within 2^-16 of the entry, relative:
+bf16 keeps 8 significant bits).
+The chunk order is the GEMM's: [n_pad/128][k_pad/16][term][k half][row],
+8 entries of one row per 16-byte chunk."""
+import numpy as np
+import pytest
+
+import synth
+import paper_2509_12086_amd as saq
+from gpu_util import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _bf16_value(h):
+    return (h.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _rne_bf16(x32):
+    u = x32.astype(np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("D,bpd", [(960, 4.0), (99, 3.0)])
+def test_plan_split_terms_sum_to_M(D, bpd):
+    X = synth.cfg2(4000).rows() if D == 960 else (
+        np.random.default_rng(3).standard_normal((4000, D)) * np.exp(-np.arange(D) / 25.0)
+    ).astype(np.float32)
+    plan = saq.Plan.fit(X, saq.PlanParams(bits_per_dim=bpd, fit_sample=0)).upload(0)
+    torch.cuda.synchronize()
+    M, _, _ = plan.arrays()
+    dk = plan.D_kept
+    n_pad = max(128, -(-dk // 128) * 128)
+    k_pad = -(-D // 32) * 32
+    say(f"split M: D={D} D_kept={dk} n_pad={n_pad} k_pad={k_pad}")
+    buf = plan._dev.cpu().numpy()
+    off = (-plan._dev.data_ptr()) % 256
+    off_ms = off + -(-(n_pad * k_pad * 4) // 256) * 256
+    nchunk = (n_pad // 128) * (k_pad // 16) * 768
+    h = buf[off_ms:off_ms + nchunk * 16].view(np.uint16)
+    # [tile][step][term][half][row][e] -> [term][tile*128 + row][step*16 + half*8 + e]
+    h = h.reshape(n_pad // 128, k_pad // 16, 3, 2, 128, 8).transpose(2, 0, 4, 1, 3, 5)
+    h = h.reshape(3, n_pad, k_pad)
+    Mp = np.zeros((n_pad, k_pad), np.float32)
+    Mp[:dk, :D] = M
+    t0, t1, t2 = (_bf16_value(h[i]) for i in range(3))
+    assert np.array_equal(t0 + t1 + t2, Mp.astype(np.float64))      # exact (FP64 sum)
+    assert np.array_equal(h[0], _rne_bf16(Mp))
+    r1 = (Mp.astype(np.float64) - t0).astype(np.float32)            # exact in FP32
+    assert np.array_equal(h[1], _rne_bf16(r1))
+    r2 = (r1.astype(np.float64) - t1).astype(np.float32)
+    assert np.array_equal(h[2], _rne_bf16(r2))
+    a = np.abs(Mp.astype(np.float64))
+    assert np.all(np.abs(Mp - t0) <= 2.0 ** -8 * a)
+    assert np.all(np.abs(Mp - t0 - t1) <= 2.0 ** -16 * a)
