@@ -188,11 +188,10 @@ def main():
     traffic_workload = f"{n:,} x {D}, {a.bpd:g} b/dim, r={a.rounds}"
     q_valu = recorded_valu("quantize_kernel", traffic_workload)
     proj_tflops = flops / (proj_ms * 1e-3) / 1e12
-    # FP32 accumulation runs the split-operand GEMM: six bf16 products per
-    # FP32 product on the bf16 matrix cores (FP64 totals: FP32 MFMAs)
-    split = not plan.info["projection_fp64_totals"]
-    mfma_flops = flops * (SPLIT_PRODUCTS if split else 1)
-    mfma_peak = PEAK_BF16_MFMA if split else PEAK_FP32_MFMA
+    # the projection forms each FP32 product as six bf16 MFMA products
+    acc64 = bool(plan.info["projection_fp64_totals"])
+    mfma_flops = flops * SPLIT_PRODUCTS
+    mfma_peak = PEAK_BF16_MFMA
     mfma_tflops = mfma_flops / (proj_ms * 1e-3) / 1e12
     q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
     q_gbs = q_bytes / (quant_ms * 1e-3) / 1e9
@@ -239,8 +238,8 @@ def main():
         },
         "roofline": {
             "kernel": ("project_kernel (o = M (x - c), FP32 products as six bf16 MFMA products "
-                       "of exactly split operands, FP32 accumulation)") if split else
-                      "project_kernel (o = M (x - c), FP32 MFMAs, FP64 k-tile totals)",
+                       "of exactly split operands, " +
+                       ("FP64 k-tile totals)" if acc64 else "FP32 accumulation)")),
             "bound": "mfma",
             "achieved": mfma_tflops,
             "peak": mfma_peak / 1e12,

@@ -35,32 +35,22 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 namespace {
 
 constexpr int TN = saq::kGemmTileN;   // 128 kept dims per tile
-constexpr int TK = saq::kGemmTileK;   // 32 input dims per k-step
-constexpr int LDS_STRIDE = TK + 4;    // floats per LDS row (conflict-free b128 reads)
 constexpr int NXCD = 8;               // MI355X: 8 XCDs, workgroups dealt round-robin
 
 enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1, LAYOUT_TILES = 2 };
 
 // ---------------------------------------------------------------------------
-// Projection GEMM, FP32-MFMA form.  Workgroup = 256 threads (4 waves)
-// computes a (64 BI) x 128 tile of O (vectors x kept dims); each wave a
-// (32 BI) x 64 part as BI x 2 32x32 MFMA blocks.  The 32-wide k-step is split
-// between the two half-waves: half h feeds k = 16h + j at MFMA step j, so
-// every lane reads 16 contiguous floats per row from LDS (4 x ds_read_b128).
+// Projection GEMM.  Workgroup = 256 threads (4 waves) computes a (64 BI) x 128
+// tile of O (vectors x kept dims); each wave a (32 BI) x 64 part as BI x 2
+// 32x32 MFMA blocks.  BI = 2 with FP32 accumulation; BI = 1 with FP64 k-tile
+// totals (64 doubles per 32 x 32 block and lane pair).
 //
 // Tile order is XCD-aware: workgroup b runs on XCD b % 8; XCD x walks row
 // tiles x, x+8, ... and, inside each, all column tiles back to back, so the
 // X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
 // ---------------------------------------------------------------------------
-// BI = 32-row MFMA blocks per wave along the vectors.  The projection takes
-// this form only with FP64 k-tile totals (64 doubles per 32 x 32 block and
-// lane pair), at BI = 1: 64 x 128 tiles, 55.3 KB of LDS, two workgroups per
-// compute unit.  FP32 accumulation runs the split-operand GEMM below.
 template <int BI> constexpr int gemm_rows() { return 64 * BI; }
-template <int BI> constexpr int gemm_lds_floats() { return 2 * (64 * BI + TN) * LDS_STRIDE; }
 
-// One (64 BI) x 128 output tile (tile_m, tile_n).  lds: gemm_lds_floats<BI>()
-// floats, free on entry and on return (the last k-step ends with a barrier).
 // Per-record reference vectors (Section 3.1's c; the IVF centroid of each
 // record's list in the paper's experiments): record i is centered on row
 // ids[i] of refs [K x D] (all records on row 0 when ids is null) instead of
@@ -101,215 +91,24 @@ __device__ __forceinline__ void store_quad(float* __restrict__ O, int64_t ld, in
     }
 }
 
-// FULLB: both of the wave's 32-column blocks hold kept dims.  Without it
-// (a wave of the last column tile whose second block lies past dk) the wave
-// runs only its first block's MFMAs; the waves of one workgroup may take
-// different variants, which share the same barrier sequence.
-template <int LAYOUT, bool ACC64, bool NORM, int BI, bool FULLB, bool REF>
-__device__ __forceinline__ void gemm_tile_impl(
-    bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
-    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
-    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
-    static_assert(BI == 1 || BI == 2, "tile shapes: 64 x 128 or 128 x 128");
-    constexpr int RM = gemm_rows<BI>();          // vectors per tile
-    constexpr int ATPR = 256 / RM;               // threads per A row (4 or 2)
-    constexpr int ALK = TK / ATPR;               // A floats per thread per k-step
-    float (*As)[RM * LDS_STRIDE] = reinterpret_cast<float (*)[RM * LDS_STRIDE]>(lds);
-    float (*Bs)[TN * LDS_STRIDE] = reinterpret_cast<float (*)[TN * LDS_STRIDE]>(lds + 2 * RM * LDS_STRIDE);
-    const int64_t m0 = int64_t(tile_m) * RM;
-    const int n0 = tile_n * TN;
-
-    const int t = threadIdx.x;
-    const int lr = t / ATPR;            // A row loaded by this thread
-    const int lk = (t % ATPR) * ALK;    // its k offset inside the tile
-    const int br = t >> 1;              // B row loaded by this thread
-    const int bk = (t & 1) * 16;
-    const int64_t arow = m0 + lr;
-    const bool arow_ok = arow < n;
-    // rows past n read row n-1 (always valid memory) and are zeroed on store
-    const float* xrow = X + (arow_ok ? arow : n - 1) * int64_t(D);
-    const float* brow = Mp + int64_t(n0 + br) * k_pad;
-    // this row's reference: the plan's c (zero padded to k_pad, shared by
-    // every row) or, with REF, its row of refs
-    const float* crow = cp;
-    bool ref_bad = false;
-    if (REF) {
-        const int32_t id = R.ids != nullptr ? R.ids[arow_ok ? arow : n - 1] : 0;
-        ref_bad = id < 0 || id >= R.K;
-        crow = R.refs + int64_t(ref_bad ? 0 : id) * D;
-    }
-    double nacc = 0.0;
-
-    // raw global values of the next tile; consumed only after the MFMAs of
-    // the current tile so the loads overlap the matrix work
-    float rx[ALK], rc[ALK], rb[16];
-    auto load_full = [&](int k0) {          // k0 + 32 <= D (and VEC)
-        const int kb = k0 + lk;
-#pragma unroll
-        for (int q = 0; q < ALK / 4; ++q) {
-            const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
-            const float4 c4 = *reinterpret_cast<const float4*>((REF ? crow : cp) + kb + 4 * q);
-            rx[4 * q + 0] = x4.x; rx[4 * q + 1] = x4.y; rx[4 * q + 2] = x4.z; rx[4 * q + 3] = x4.w;
-            rc[4 * q + 0] = c4.x; rc[4 * q + 1] = c4.y; rc[4 * q + 2] = c4.z; rc[4 * q + 3] = c4.w;
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 b4 = *reinterpret_cast<const float4*>(brow + k0 + bk + 4 * q);
-            rb[4 * q + 0] = b4.x; rb[4 * q + 1] = b4.y; rb[4 * q + 2] = b4.z; rb[4 * q + 3] = b4.w;
-        }
-    };
-    auto load_guarded = [&](int k0) {       // any tile: element loads below D
-        const int kb = k0 + lk;
-#pragma unroll
-        for (int e = 0; e < ALK; ++e) {
-            rx[e] = (kb + e < D) ? xrow[kb + e] : 0.f;
-            rc[e] = REF ? ((kb + e < D) ? crow[kb + e] : 0.f) : cp[kb + e];
-        }
-#pragma unroll
-        for (int e = 0; e < 16; ++e) rb[e] = brow[k0 + bk + e];
-    };
-    // rows past n hold row n-1: their outputs and norms are never stored
-    auto store_tile = [&](int buf) {
-        float ra[ALK];
-#pragma unroll
-        for (int e = 0; e < ALK; ++e) {
-            ra[e] = rx[e] - rc[e];
-            if (NORM) {
-                // exact (x - c)^2 in FP64; padding entries are 0 - 0
-                const double d = double(rx[e]) - double(rc[e]);
-                nacc = fma(d, d, nacc);
-            }
-        }
-        float* a = &As[buf][lr * LDS_STRIDE + lk];
-        float* b = &Bs[buf][br * LDS_STRIDE + bk];
-#pragma unroll
-        for (int q = 0; q < ALK / 4; ++q)
-            *reinterpret_cast<float4*>(a + 4 * q) = make_float4(ra[4 * q], ra[4 * q + 1], ra[4 * q + 2], ra[4 * q + 3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            *reinterpret_cast<float4*>(b + 4 * q) = make_float4(rb[4 * q], rb[4 * q + 1], rb[4 * q + 2], rb[4 * q + 3]);
-    };
-    // full tiles use 16-byte loads when the rows allow it
-    const int kfull = vec ? (D / TK) : 0;
-    auto load_tile = [&](int kt) {
-        if (kt < kfull) load_full(kt * TK); else load_guarded(kt * TK);
-    };
-
-    const int wave = t >> 6, lane = t & 63;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int li = lane & 31, lh = lane >> 5;
-    // ACC64: each 32-wide k-tile is accumulated by the MFMAs in FP32 from
-    // zero and then added into FP64 totals, so the FP32 rounding error grows
-    // with the tile length (32) rather than with D.  Otherwise the MFMAs
-    // accumulate the whole dot product in FP32.
-    floatx16 acc[BI][2];
-    double tot[BI][2][ACC64 ? 16 : 1];
-#pragma unroll
-    for (int i = 0; i < BI; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-#pragma unroll
-            for (int r = 0; r < (ACC64 ? 16 : 1); ++r) tot[i][j][r] = 0.0;
-        }
-
-    const int ktiles = k_pad / TK;
-    load_tile(0);
-    store_tile(0);
-    __syncthreads();
-    for (int kt = 0; kt < ktiles; ++kt) {
-        const int buf = kt & 1;
-        const bool more = kt + 1 < ktiles;
-        if (more) load_tile(kt + 1);
-        const float* a0 = &As[buf][(wm * (32 * BI) + li) * LDS_STRIDE + lh * 16];
-        const float* b0 = &Bs[buf][(wn * 64 + li) * LDS_STRIDE + lh * 16];
-        const float* b1 = b0 + 32 * LDS_STRIDE;
-        float A[BI][16], B0[16], B1[16];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-            for (int i = 0; i < BI; ++i) {
-                const float4 va = *reinterpret_cast<const float4*>(a0 + i * 32 * LDS_STRIDE + 4 * q);
-                A[i][4 * q] = va.x; A[i][4 * q + 1] = va.y; A[i][4 * q + 2] = va.z; A[i][4 * q + 3] = va.w;
-            }
-            const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
-            const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
-            B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
-            B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
-        }
-#pragma unroll
-        for (int j = 0; j < 16; ++j) {
-#pragma unroll
-            for (int i = 0; i < BI; ++i) {
-                acc[i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B0[j], acc[i][0], 0, 0, 0);
-                if (FULLB)
-                    acc[i][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i][j], B1[j], acc[i][1], 0, 0, 0);
-            }
-        }
-        if (ACC64) {
-#pragma unroll
-            for (int i = 0; i < BI; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        tot[i][j][r & (ACC64 ? 15 : 0)] += double(acc[i][j][r]);
-                        acc[i][j][r] = 0.f;
-                    }
-        }
-        if (more) store_tile(buf ^ 1);
-        __syncthreads();
-    }
-
-    if (NORM) {
-        // the ATPR threads of a row are adjacent lanes
-        if (ATPR >= 2) nacc += __shfl_xor(nacc, 1);
-        if (ATPR >= 4) nacc += __shfl_xor(nacc, 2);
-        if ((t % ATPR) == 0 && arow_ok) norm2[arow] = ref_bad ? __builtin_nanf("") : float(nacc);
-    }
-
-    // epilogue: lane holds column n0 + wn*64 + 32*bj + li and, for register
-    // r, row m0 + wm*32*BI + 32*bi + 8*(r/4) + 4*lh + r%4
-#pragma unroll
-    for (int bi = 0; bi < BI; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int col = n0 + wn * 64 + bj * 32 + li;
-            if (col >= dk) continue;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int64_t row = m0 + wm * (32 * BI) + bi * 32 + 8 * g + 4 * lh;
-                float v0, v1, v2, v3;
-                if (ACC64) {
-                    v0 = float(tot[bi][bj][(4 * g + 0) & (ACC64 ? 15 : 0)]);
-                    v1 = float(tot[bi][bj][(4 * g + 1) & (ACC64 ? 15 : 0)]);
-                    v2 = float(tot[bi][bj][(4 * g + 2) & (ACC64 ? 15 : 0)]);
-                    v3 = float(tot[bi][bj][(4 * g + 3) & (ACC64 ? 15 : 0)]);
-                } else {
-                    v0 = acc[bi][bj][4 * g + 0]; v1 = acc[bi][bj][4 * g + 1];
-                    v2 = acc[bi][bj][4 * g + 2]; v3 = acc[bi][bj][4 * g + 3];
-                }
-                store_quad<LAYOUT>(O, ld, n, row, col, v0, v1, v2, v3);
-            }
-        }
-}
-
-
 // ---------------------------------------------------------------------------
-// Split-operand projection (FP32 accumulation).  Every FP32 operand a is
+// Split-operand projection.  Every FP32 operand a is
 // written exactly as a0 + a1 + a2 in bf16 (RNE to 8 significant bits, then
 // RNE of the exact remainder, twice), and a b as the six products a_i b_j
 // with i + j <= 2, the bf16x6 scheme of Henry, Tang and Heinecke (2019).  The
 // three dropped products are below 2^-24 |a b| together, the size of one FP32
 // rounding, and the MFMAs (v_mfma_f32_32x32x16_bf16) accumulate in FP32, so
 // o keeps FP32 accuracy; the bf16 matrix rate is 16x the FP32 one, so the six
-// products take 3/8 of the FP32 MFMA time.
+// products take 3/8 of the FP32 MFMA time.  With ACC64 each 32-wide k-tile
+// (two k-steps) is accumulated in FP32 from zero and then added into FP64
+// totals, so the FP32 rounding error grows with the tile length (32) rather
+// than with D.
 //
 // Tile (64 BI) x 128, k-step 16, four waves of (32 BI) x 64 (BI x 2 blocks
-// of 32 x 32); BI = 2 for the plain launches, 1 in grouped launches that
-// also carry FP64-total datasets.  Every output element sees the same MFMA
-// sequence over k in both shapes, so they give identical results.  Per
+// of 32 x 32); BI = 2 for FP32 accumulation, 1 for FP64 totals and in
+// grouped launches that also carry FP64-total datasets.  Every output element
+// sees the same MFMA sequence over k in both shapes, so they give identical
+// results.  Per
 // buffer, LDS holds both operands as 16-byte chunks [A|B][term][k half]
 // [row]: a lane's MFMA operand (8 bf16 of one row, k half = lane / 32) is one
 // chunk, and a wave reads two contiguous 512-byte runs.  The X rows are split
@@ -320,7 +119,7 @@ __device__ __forceinline__ void gemm_tile_impl(
 // global load, so X and the B chunks are loaded two k-steps ahead into
 // alternating register sets.  For BI = 2, 48 KB of LDS and at most 168 VGPRs
 // give three workgroups per compute unit (two with per-row references,
-// whose extra c registers would spill at three).
+// whose extra c registers would spill at three); FP64 totals run two.
 // ---------------------------------------------------------------------------
 constexpr int SK = saq::kSplitK;              // input dims per k-step
 constexpr int SCB = saq::kSplitChunks;        // B chunks per buffer
@@ -344,7 +143,7 @@ __device__ __forceinline__ floatx16 mfma_bf16(u32x4 a, u32x4 b, floatx16 c) {
 
 // lds: split_lds_floats<BI>() floats, free on entry; on return free except
 // after a NORM tile (the norm hand-off leaves a barrier-protected write).
-template <int LAYOUT, bool NORM, int BI, bool FULLB, bool REF>
+template <int LAYOUT, bool NORM, int BI, bool FULLB, bool REF, bool ACC64>
 __device__ __forceinline__ void gemm_split_tile_impl(
     bool vec, const float* __restrict__ X, int64_t n, int D, const u32x4* __restrict__ Ms,
     int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
@@ -442,12 +241,16 @@ __device__ __forceinline__ void gemm_split_tile_impl(
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 31, lh = lane >> 5;
     floatx16 acc[BI][2];
+    double tot[BI][2][ACC64 ? 16 : 1];
 #pragma unroll
     for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+#pragma unroll
+            for (int r = 0; r < (ACC64 ? 16 : 1); ++r) tot[i][j][r] = 0.0;
+        }
 
     auto kstep = [&](int kt, const Stage& cur, Stage& nxt) {
         const int buf = kt & 1;
@@ -472,6 +275,18 @@ __device__ __forceinline__ void gemm_split_tile_impl(
                 acc[i][0] = mfma_bf16(a[i][TA[u]], b[0][TB[u]], acc[i][0]);
                 if (FULLB) acc[i][1] = mfma_bf16(a[i][TA[u]], b[1][TB[u]], acc[i][1]);
             }
+        if (ACC64 && (kt & 1)) {
+            // end of a 32-wide k-tile: into the FP64 totals
+#pragma unroll
+            for (int i = 0; i < BI; ++i)
+#pragma unroll
+                for (int j = 0; j < (FULLB ? 2 : 1); ++j)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        tot[i][j][r & (ACC64 ? 15 : 0)] += double(acc[i][j][r]);
+                        acc[i][j][r] = 0.f;
+                    }
+        }
         if (kt + 1 < ksteps) store_step(kt + 1, buf ^ 1, cur);
         __syncthreads();
     };
@@ -504,59 +319,49 @@ __device__ __forceinline__ void gemm_split_tile_impl(
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int64_t row = m0 + wm * (32 * BI) + bi * 32 + 8 * g + 4 * lh;
-                store_quad<LAYOUT>(O, ld, n, row, col, acc[bi][bj][4 * g + 0], acc[bi][bj][4 * g + 1],
-                                   acc[bi][bj][4 * g + 2], acc[bi][bj][4 * g + 3]);
+                if (ACC64)
+                    store_quad<LAYOUT>(O, ld, n, row, col,
+                                       float(tot[bi][bj][(4 * g + 0) & (ACC64 ? 15 : 0)]),
+                                       float(tot[bi][bj][(4 * g + 1) & (ACC64 ? 15 : 0)]),
+                                       float(tot[bi][bj][(4 * g + 2) & (ACC64 ? 15 : 0)]),
+                                       float(tot[bi][bj][(4 * g + 3) & (ACC64 ? 15 : 0)]));
+                else
+                    store_quad<LAYOUT>(O, ld, n, row, col, acc[bi][bj][4 * g + 0],
+                                       acc[bi][bj][4 * g + 1], acc[bi][bj][4 * g + 2],
+                                       acc[bi][bj][4 * g + 3]);
             }
         }
 }
 
-// One output tile: FP32 accumulation runs the split-operand GEMM, FP64
-// k-tile totals the FP32 MFMAs.  ||x - c||^2 is produced by the first column
-// tile only; the k-loop is specialised so the other tiles carry none of its
-// work.
+// One output tile.  ||x - c||^2 is produced by the first column tile only;
+// the k-loop is specialised so the other tiles carry none of its work.
 template <int LAYOUT, bool ACC64, int BI, bool REF = false>
 __device__ __forceinline__ void gemm_tile(
-    bool vec, const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
-    const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
-    float* __restrict__ O, int64_t ld, float* __restrict__ norm2, int tile_m, int tile_n,
-    float* __restrict__ lds, RefRows R) {
+    bool vec, const float* __restrict__ X, int64_t n, int D, const u32x4* __restrict__ Ms,
+    int k_pad, const float* __restrict__ cp, int dk, float* __restrict__ O, int64_t ld,
+    float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
     // the wave's second 32-column block (wave w covers columns
     // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
     const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
-    if constexpr (!ACC64) {
-        if (norm2 != nullptr && tile_n == 0)
-            gemm_split_tile_impl<LAYOUT, true, BI, true, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
-                                                              ld, norm2, tile_m, tile_n, lds, R);
-        else if (fullb)
-            gemm_split_tile_impl<LAYOUT, false, BI, true, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
-                                                               ld, norm2, tile_m, tile_n, lds, R);
-        else
-            gemm_split_tile_impl<LAYOUT, false, BI, false, REF>(vec, X, n, D, Ms, k_pad, cp, dk, O,
-                                                                ld, norm2, tile_m, tile_n, lds, R);
-    } else {
-        if (norm2 != nullptr && tile_n == 0)
-            gemm_tile_impl<LAYOUT, true, true, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
-                                                              ld, norm2, tile_m, tile_n, lds, R);
-        else if (fullb)
-            gemm_tile_impl<LAYOUT, true, false, BI, true, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
-                                                               ld, norm2, tile_m, tile_n, lds, R);
-        else
-            gemm_tile_impl<LAYOUT, true, false, BI, false, REF>(vec, X, n, D, Mp, k_pad, cp, dk, O,
-                                                                ld, norm2, tile_m, tile_n, lds, R);
-    }
+    if (norm2 != nullptr && tile_n == 0)
+        gemm_split_tile_impl<LAYOUT, true, BI, true, REF, ACC64>(vec, X, n, D, Ms, k_pad, cp, dk,
+                                                                 O, ld, norm2, tile_m, tile_n, lds, R);
+    else if (fullb)
+        gemm_split_tile_impl<LAYOUT, false, BI, true, REF, ACC64>(vec, X, n, D, Ms, k_pad, cp, dk,
+                                                                  O, ld, norm2, tile_m, tile_n, lds, R);
+    else
+        gemm_split_tile_impl<LAYOUT, false, BI, false, REF, ACC64>(vec, X, n, D, Ms, k_pad, cp, dk,
+                                                                   O, ld, norm2, tile_m, tile_n, lds,
+                                                                   R);
 }
 
-// FP32 accumulation runs the 128 x 128 split-operand tile, FP64 k-tile
-// totals the 64 x 128 FP32-MFMA tile
+// FP32 accumulation runs the 128 x 128 tile, FP64 k-tile totals the 64 x 128
 template <bool ACC64> constexpr int gemm_bi() { return ACC64 ? 1 : 2; }
-template <bool ACC64> constexpr int gemm_lds_size() {
-    return ACC64 ? gemm_lds_floats<1>() : split_lds_floats<2>();
-}
+template <bool ACC64> constexpr int gemm_lds_size() { return split_lds_floats<gemm_bi<ACC64>()>(); }
 
 template <bool VEC, int LAYOUT, bool ACC64, bool REF>
-__global__ __launch_bounds__(256, ACC64 ? 1 : (REF ? 2 : 3)) void project_kernel(
-    const float* __restrict__ X, int64_t n, int D, const float* __restrict__ Mp,
-    const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
+__global__ __launch_bounds__(256, (ACC64 || REF) ? 2 : 3) void project_kernel(
+    const float* __restrict__ X, int64_t n, int D, const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
     float* __restrict__ O, int64_t ld, float* __restrict__ norm2, int tiles_m, int tiles_n,
     RefRows R) {
     constexpr int BI = gemm_bi<ACC64>();
@@ -566,8 +371,8 @@ __global__ __launch_bounds__(256, ACC64 ? 1 : (REF ? 2 : 3)) void project_kernel
     const int tile_n = local % tiles_n;
     const int tile_m = (local / tiles_n) * NXCD + xcd;
     if (tile_m >= tiles_m) return;
-    gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Mp, Ms, k_pad, cp, dk, O, ld, norm2, tile_m,
-                                      tile_n, lds, R);
+    gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Ms, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n,
+                                      lds, R);
 }
 
 // ---------------------------------------------------------------------------
@@ -853,14 +658,14 @@ constexpr int BATCH_MAX = 16;
 
 struct GemmSet {
     const float* X; int64_t n; int D; int vec; int acc64;
-    const float* Mp; const u32x4* Ms; int k_pad; const float* cp; int dk; int tiles_m; int tiles_n;
+    const u32x4* Ms; int k_pad; const float* cp; int dk; int tiles_m; int tiles_n;
     float* O; int64_t ld; float* norm2;
     int64_t first_block;
 };
 struct GemmArgs { GemmSet set[BATCH_MAX]; int count; int xcd_order; };
 
 template <bool ACC64>
-__global__ __launch_bounds__(256, ACC64 ? 1 : 3) void grouped_gemm_kernel(const GemmArgs args) {
+__global__ __launch_bounds__(256, ACC64 ? 2 : 3) void grouped_gemm_kernel(const GemmArgs args) {
     constexpr int BI = gemm_bi<ACC64>();
     __shared__ __attribute__((aligned(16))) float lds[gemm_lds_size<ACC64>()];
     const int64_t b = blockIdx.x;
@@ -884,11 +689,11 @@ __global__ __launch_bounds__(256, ACC64 ? 1 : 3) void grouped_gemm_kernel(const 
     // one tile shape per launch: in a launch with FP64 totals, datasets
     // without them accumulate in FP32 on the same tile
     if (S.acc64)
-        gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.Ms, S.k_pad, S.cp, S.dk,
+        gemm_tile<LAYOUT_TILES, ACC64, BI>(S.vec != 0, S.X, S.n, S.D, S.Ms, S.k_pad, S.cp, S.dk,
                                           S.O, S.ld, S.norm2, tile_m, tile_n, lds,
                                           RefRows{nullptr, nullptr, 0});
     else
-        gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Mp, S.Ms, S.k_pad, S.cp, S.dk,
+        gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Ms, S.k_pad, S.cp, S.dk,
                                           S.O, S.ld, S.norm2, tile_m, tile_n, lds,
                                           RefRows{nullptr, nullptr, 0});
 }
@@ -1272,9 +1077,6 @@ saq_status check_plan(const saq_plan* p, const char* what = "plan") {
 const u32x4* dev_Ms(const saq_plan* p) {
     return reinterpret_cast<const u32x4*>(static_cast<const char*>(p->dev) + p->layout.off_Ms);
 }
-const float* dev_M(const saq_plan* p) {
-    return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_M);
-}
 const float* dev_c(const saq_plan* p) {
     return reinterpret_cast<const float*>(static_cast<const char*>(p->dev) + p->layout.off_c);
 }
@@ -1302,9 +1104,8 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
     if (layout == LAYOUT_TILES && (reinterpret_cast<uintptr_t>(O) & 15) != 0)
         return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
 #define SAQ_LAUNCH_PROJ(V, L, A, F)                                                               \
-    hipLaunchKernelGGL((project_kernel<V, L, A, F>), grid, dim3(256), 0, st, X, n, p->D, dev_M(p),\
-                       dev_Ms(p), p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m,  \
-                       tiles_n, R)
+    hipLaunchKernelGGL((project_kernel<V, L, A, F>), grid, dim3(256), 0, st, X, n, p->D, dev_Ms(p),\
+                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R)
 #define SAQ_LAUNCH_PROJ2(V, L, F) \
     do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true, F); else SAQ_LAUNCH_PROJ(V, L, false, F); } while (0)
     // references per row exist for the tiled (encode) and row (query) layouts
@@ -1430,7 +1231,7 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         GemmSet& G = B.g.set[B.g.count++];
         G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
         G.vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
-        G.Mp = dev_M(p); G.Ms = dev_Ms(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
+        G.Ms = dev_Ms(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
         const int rows = B.any64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
         G.tiles_m = int((it.n + rows - 1) / rows); G.tiles_n = p->layout.n_pad / TN;
         G.O = O; G.ld = ld; G.norm2 = nrm;

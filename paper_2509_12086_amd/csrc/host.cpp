@@ -33,8 +33,7 @@ DeviceLayout device_layout(const saq_plan& p) {
     DeviceLayout L;
     L.n_pad = std::max(kGemmTileN, (p.D_kept + kGemmTileN - 1) / kGemmTileN * kGemmTileN);
     L.k_pad = (p.D + kGemmTileK - 1) / kGemmTileK * kGemmTileK;
-    L.off_M = 0;
-    L.off_Ms = align256(L.off_M + int64_t(L.n_pad) * L.k_pad * 4);
+    L.off_Ms = 0;
     const int64_t split_chunks = int64_t(L.n_pad / kGemmTileN) * (L.k_pad / kSplitK) * kSplitChunks;
     L.off_c = align256(L.off_Ms + split_chunks * 16);
     L.off_seg = align256(L.off_c + int64_t(L.k_pad) * 4);
@@ -62,10 +61,8 @@ void build_staging(saq_plan& p) {
     p.layout = device_layout(p);
     const DeviceLayout& L = p.layout;
     p.staging.assign(size_t(L.bytes), 0);
-    float* M = reinterpret_cast<float*>(p.staging.data() + L.off_M);
-    for (int32_t r = 0; r < p.D_kept; ++r)
-        std::memcpy(M + int64_t(r) * L.k_pad, p.M.data() + int64_t(r) * p.D, size_t(p.D) * 4);
-    // M_split: each entry as three bf16 terms, in the GEMM's chunk order
+    // M_split: each entry of M, zero padded to [n_pad x k_pad], as three bf16
+    // terms, in the GEMM's chunk order
     uint16_t* Ms = reinterpret_cast<uint16_t*>(p.staging.data() + L.off_Ms);
     const int ksteps = L.k_pad / kSplitK;
     for (int tile = 0; tile < L.n_pad / kGemmTileN; ++tile)
@@ -73,7 +70,8 @@ void build_staging(saq_plan& p) {
             for (int half = 0; half < 2; ++half)
                 for (int row = 0; row < kGemmTileN; ++row)
                     for (int e = 0; e < 8; ++e) {
-                        float v = M[int64_t(tile * kGemmTileN + row) * L.k_pad + ks * kSplitK + 8 * half + e];
+                        const int r = tile * kGemmTileN + row, k = ks * kSplitK + 8 * half + e;
+                        float v = (r < p.D_kept && k < p.D) ? p.M[int64_t(r) * p.D + k] : 0.0f;
                         for (int term = 0; term < 3; ++term) {
                             const uint16_t h = bf16_rne(v);
                             const int64_t chunk = (int64_t(tile) * ksteps + ks) * kSplitChunks +

@@ -11,8 +11,8 @@
 namespace saq {
 
 // Device plan layout (one caller-owned buffer, every region 256-byte aligned):
-//   M_pad   float [n_pad x k_pad]   rows = kept dims in plan order, zero padded
-//   M_split 16-byte chunks [n_pad/128][k_pad/16][3][2][128]: M_pad written as
+//   M_split 16-byte chunks [n_pad/128][k_pad/16][3][2][128]: M (rows = kept
+//           dims in plan order) zero padded to [n_pad x k_pad] and written as
 //           three bf16 terms per entry (m = m0 + m1 + m2, each the RNE bf16 of
 //           what the previous terms leave), chunk (tile, step, term, half, row)
 //           holding entries k = 16 step + 8 half .. + 7 of row 128 tile + row,
@@ -22,8 +22,8 @@ namespace saq {
 //   S       float [sum_s W_s^2]     per kept segment, row-major W x W blocks
 //                                   sqrt(sigma_i^2) R_s^T (one float if absent)
 constexpr int kGemmTileN = 128;   // GEMM tile along the kept dims
-constexpr int kGemmTileK = 32;    // GEMM tile along the input dims
-constexpr int kGemmTileM = 128;   // GEMM tile along the vectors
+constexpr int kGemmTileK = 32;    // k_pad granularity: the GEMM's k-steps of 16 run in
+                                  // pairs (32-wide k-tiles for FP64 totals)
 constexpr int kSplitK = 16;       // k-step of the split-operand GEMM
 constexpr int kSplitChunks = 3 * 2 * kGemmTileN;   // 16-byte chunks per tile and k-step
 
@@ -36,7 +36,7 @@ struct SegEntry {
 
 struct DeviceLayout {
     int32_t n_pad = 0, k_pad = 0;
-    int64_t off_M = 0, off_Ms = 0, off_c = 0, off_seg = 0, off_S = 0, bytes = 0;
+    int64_t off_Ms = 0, off_c = 0, off_seg = 0, off_S = 0, bytes = 0;
 };
 
 }  // namespace saq

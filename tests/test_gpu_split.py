@@ -43,7 +43,7 @@ def test_plan_split_terms_sum_to_M(D, bpd):
     say(f"split M: D={D} D_kept={dk} n_pad={n_pad} k_pad={k_pad}")
     buf = plan._dev.cpu().numpy()
     off = (-plan._dev.data_ptr()) % 256
-    off_ms = off + -(-(n_pad * k_pad * 4) // 256) * 256
+    off_ms = off                     # the first region of the plan buffer
     nchunk = (n_pad // 128) * (k_pad // 16) * 768
     h = buf[off_ms:off_ms + nchunk * 16].view(np.uint16)
     # [tile][step][term][half][row][e] -> [term][tile*128 + row][step*16 + half*8 + e]
