@@ -12,9 +12,10 @@ The chunk order is the GEMM's: [n_pad/128][k_pad/16][term][k half][row],
 import numpy as np
 import pytest
 
+import oracle
 import synth
 import paper_2509_12086_amd as saq
-from gpu_util import say
+from gpu_util import say, to_dev
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -61,3 +62,32 @@ def test_plan_split_terms_sum_to_M(D, bpd):
     a = np.abs(Mp.astype(np.float64))
     assert np.all(np.abs(Mp - t0) <= 2.0 ** -8 * a)
     assert np.all(np.abs(Mp - t0 - t1) <= 2.0 ** -16 * a)
+
+
+@pytest.mark.parametrize("e", [-50, 50])
+def test_encode_is_exactly_scale_equivariant(e):
+    """Scaling X and c by 2^e commutes with every step of the encode: the
+    three-term split, the MFMA products and FP32 sums, the grid, the FP64
+    adjustment decisions and the factors.  So the records must be the
+    unscaled ones bit for bit, the factors exactly 2^e times and the norms
+    2^(2e) times, on both accumulations (FP32, and FP64 k-tile totals), on a
+    ragged row count."""
+    X = synth.cfg2(6000).rows()[:4999]
+    mean, _, lam, V = oracle.pca(X)
+    c0 = mean.astype(np.float32).astype(np.float64)
+    s = np.float32(2.0 ** e)
+    for mode in (1, 2):
+        params = saq.PlanParams(bits_per_dim=4.0, projection_accumulation=mode)
+        p0 = saq.Plan.from_basis(c0, V, lam, params).upload(0)
+        p1 = saq.Plan.from_basis(c0 * 2.0 ** e, V, lam, params).upload(0)
+        assert p0.widths == p1.widths and p0.bits == p1.bits
+        assert np.array_equal(p0.arrays()[0], p1.arrays()[0])
+        say(f"scale 2^{e}, accumulation mode {mode}")
+        r0, f0 = saq.encode(p0, to_dev(X), 4)
+        r1, f1 = saq.encode(p1, to_dev(X * s), 4)
+        torch.cuda.synchronize()
+        assert torch.equal(r0, r1)
+        f0, f1 = f0.cpu().numpy().astype(np.float64), f1.cpu().numpy().astype(np.float64)
+        k = len(p0.kept_widths)
+        assert np.array_equal(f1[:, :k], f0[:, :k] * 2.0 ** e)
+        assert np.array_equal(f1[:, k], f0[:, k] * 2.0 ** (2 * e))
