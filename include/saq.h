@@ -64,11 +64,11 @@ typedef struct {
     int64_t  fit_sample;      /* rows used for mean/covariance (0 = all); an evenly spaced subset */
     uint64_t seed;            /* seeds the per-segment rotations */
     int32_t  projection_accumulation; /* 0 auto: FP64 k-tile totals when D > 1024 or a kept
-                                         segment has >= 8 bits, else FP32; 1: FP32 throughout
-                                         (each FP32 product formed as six bf16 matrix-core
-                                         products of exactly split operands, error below one
-                                         FP32 rounding); 2: FP32 MFMAs per 32-wide k-tile,
-                                         FP64 across tiles */
+                                         segment has >= 8 bits, else FP32; 1: FP32 throughout;
+                                         2: FP32 per 32-wide k-tile, FP64 across tiles.  Every
+                                         FP32 product is formed as six bf16 matrix-core
+                                         products of operands split exactly into three bf16
+                                         terms (error below one FP32 rounding). */
 } saq_plan_params;
 
 typedef struct {

@@ -1,12 +1,11 @@
 // Device half of libsaq.so (gfx950): the SAQ encode hot path and the
 // estimate scan, plus their C-ABI entry points.
 //
-//   project_kernel   o = M (x - c) as a matrix-core GEMM with FP32
-//                    accumulation: FP32 products formed exactly from split
-//                    bf16 operands (v_mfma_f32_32x32x16_bf16), or FP32
-//                    MFMAs (v_mfma_f32_32x32x2_f32) with FP64 k-tile totals;
-//                    centering fused into the A-tile load, exact FP64
-//                    ||x - c||^2 on the side.
+//   project_kernel   o = M (x - c) as a matrix-core GEMM: each FP32 product
+//                    formed from operands split exactly into bf16 terms
+//                    (v_mfma_f32_32x32x16_bf16), accumulated in FP32 or in
+//                    FP64 totals of 32-wide k-tiles; centering fused into
+//                    the A-tile staging, exact FP64 ||x - c||^2 on the side.
 //   quantize_kernel  per (vector, kept segment): v_max, the grid code of
 //                    Eq. (find_nearest_code), the code adjustment of
 //                    Algorithm 1 with FP64 decisions, the factor and the
