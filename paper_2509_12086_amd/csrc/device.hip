@@ -116,7 +116,10 @@ __device__ __forceinline__ void store_quad(float* __restrict__ O, int64_t ld, in
 // from the plan in the same chunk order, one 16-byte copy per chunk.  A
 // k-step has only 24 MFMAs per wave (768 cycles), too short to cover a
 // global load, so X and the B chunks are loaded two k-steps ahead into
-// alternating register sets.  For BI = 2, 48 KB of LDS and at most 168 VGPRs
+// alternating register sets.  The bulk of the k-steps runs in a loop whose
+// loads are all full-width and unconditional: after the ragged-tail branch
+// the compiler can no longer count the loads in flight, and its wait before
+// each A-tile store then also covered the loads issued for two steps ahead.  For BI = 2, 48 KB of LDS and at most 168 VGPRs
 // give three workgroups per compute unit (two with per-row references,
 // whose extra c registers would spill at three); FP64 totals run two.
 // ---------------------------------------------------------------------------
@@ -183,10 +186,10 @@ __device__ __forceinline__ void gemm_split_tile_impl(
     struct Stage { float x[8]; float c[8]; u32x4 b[3]; };
     Stage sA, sB;
     const int kfull = vec ? (D / SK) : 0;
-    auto load_stage = [&](int kt, Stage& g) {
+    auto load_stage = [&](int kt, Stage& g, auto fast) {
         if (stager) {
             const int kb = kt * SK + 8 * kh;
-            if (kt < kfull) {
+            if (decltype(fast)::value || kt < kfull) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const float4 x4 = *reinterpret_cast<const float4*>(xrow + kb + 4 * q);
@@ -251,9 +254,11 @@ __device__ __forceinline__ void gemm_split_tile_impl(
             for (int r = 0; r < (ACC64 ? 16 : 1); ++r) tot[i][j][r] = 0.0;
         }
 
-    auto kstep = [&](int kt, const Stage& cur, Stage& nxt) {
+    // fast: steps kt + 1 and kt + 2 exist and are full (16-byte X loads)
+    auto kstep = [&](int kt, const Stage& cur, Stage& nxt, auto fast) {
+        constexpr bool F = decltype(fast)::value;
         const int buf = kt & 1;
-        if (kt + 2 < ksteps) load_stage(kt + 2, nxt);
+        if (F || kt + 2 < ksteps) load_stage(kt + 2, nxt, fast);
         const u32x4* Ar = L + buf * SCH + lh * RM + wm * (32 * BI) + li;
         const u32x4* Br = L + buf * SCH + SCA + lh * TN + wn * 64 + li;
         u32x4 a[BI][3], b[2][3];
@@ -286,16 +291,23 @@ __device__ __forceinline__ void gemm_split_tile_impl(
                         acc[i][j][r] = 0.f;
                     }
         }
-        if (kt + 1 < ksteps) store_step(kt + 1, buf ^ 1, cur);
+        if (F || kt + 1 < ksteps) store_step(kt + 1, buf ^ 1, cur);
         __syncthreads();
     };
-    load_stage(0, sA);
+    load_stage(0, sA, std::false_type{});
     store_step(0, 0, sA);
-    load_stage(1, sB);              // k_pad is a multiple of 32: ksteps >= 2, even
+    load_stage(1, sB, std::false_type{});   // k_pad is a multiple of 32: ksteps >= 2, even
     __syncthreads();
-    for (int kt = 0; kt < ksteps; kt += 2) {
-        kstep(kt, sB, sA);
-        kstep(kt + 1, sA, sB);
+    // the bulk of the steps with branch-free loads, so the compiler's wait
+    // before each store covers only the loads that store needs
+    int kt = 0;
+    for (; kt + 3 < kfull; kt += 2) {
+        kstep(kt, sB, sA, std::true_type{});
+        kstep(kt + 1, sA, sB, std::true_type{});
+    }
+    for (; kt < ksteps; kt += 2) {
+        kstep(kt, sB, sA, std::false_type{});
+        kstep(kt + 1, sA, sB, std::false_type{});
     }
 
     if (NORM) {
