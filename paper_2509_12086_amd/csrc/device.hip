@@ -417,6 +417,12 @@ struct LaneView {
 
     __device__ __forceinline__ int64_t stride() const { return LAYOUT == LAYOUT_TILES ? 64 : sd; }
 
+    // dims j0 .. j0+QCH-1, all inside the segment
+    __device__ __forceinline__ void load_full(float (&dst)[QCH], int col, int j0) const {
+        const float* q = p + int64_t(col + j0) * stride();
+#pragma unroll
+        for (int t = 0; t < QCH; ++t) dst[t] = q[int64_t(t) * stride()];
+    }
     // dims j0 .. j0+QCH-1 of the segment starting at kept dim col; dims past
     // its width W are clamped to its last dim (loaded, never used)
     __device__ __forceinline__ void load(float (&dst)[QCH], int col, int j0, int W) const {
@@ -443,7 +449,19 @@ __device__ __forceinline__ void sweep(const LaneView<LAYOUT>& lv, int col, int W
         if (i0 + QCH <= W) body(x, i0, std::true_type{});
         else body(x, i0, std::false_type{});
     };
-    for (int i0 = 0;;) {
+    int i0 = 0;
+    // steady state, two chunks per trip: every chunk used and every chunk
+    // loaded is whole, so the loads are unconditional and the compiler's
+    // wait before a chunk's use covers only that chunk's loads (behind the
+    // whole/ragged branch it also waited for most of the next chunk's)
+    while (i0 + 3 * QCH <= W) {
+        lv.load_full(b, col, i0 + QCH);
+        body(a, i0, std::true_type{});
+        lv.load_full(a, col, i0 + 2 * QCH);
+        body(b, i0 + QCH, std::true_type{});
+        i0 += 2 * QCH;
+    }
+    for (;;) {
         const bool more = i0 + QCH < W;
         lv.load(b, col, more ? i0 + QCH : 0, W);
         run(a, i0);
