@@ -91,3 +91,41 @@ def test_encode_is_exactly_scale_equivariant(e):
         k = len(p0.kept_widths)
         assert np.array_equal(f1[:, :k], f0[:, :k] * 2.0 ** e)
         assert np.array_equal(f1[:, k], f0[:, k] * 2.0 ** (2 * e))
+
+
+@pytest.mark.parametrize("bits", [4, 8])
+@pytest.mark.parametrize("D", [16, 32, 48, 64, 80, 100, 132, 200, 515])
+def test_projection_k_loop_boundaries(D, bits):
+    """The projection's k-loop runs its bulk with unconditional 16-byte loads
+    and the ragged end through element loads.  Input dimensions around those
+    boundaries (no bulk trips below 48, a ragged 16-byte tail at 100, odd D),
+    FP32 accumulation (4-bit segment) and FP64 k-tile totals (8-bit): the
+    projection stays within the FP32 dot-product bound of the FP64 one, the
+    norm is the FP64 ||x - c||^2 rounded once, and a misaligned copy of the
+    same rows (element loads only) gives the same bits."""
+    rng = np.random.default_rng(10 * D + bits)
+    n = 333
+    X = (rng.standard_normal((n, D)) * 3.0 + 5.0).astype(np.float32)
+    c = (5.0 + 0.1 * rng.standard_normal(D)).astype(np.float32)
+    Q, _ = np.linalg.qr(rng.standard_normal((D, D)))
+    M = Q.T.astype(np.float32)
+    widths = [D] if D <= 512 else [512, D - 512]
+    plan = saq.Plan.from_parts(widths, [bits] * len(widths), M, c).upload(0)
+    assert plan.info["projection_fp64_totals"] == (bits >= 8)
+    say(f"projection D={D} bits={bits} fp64_totals={bits >= 8}")
+    Xd = to_dev(X)
+    O, n2 = saq.project(plan, Xd)
+    buf = torch.empty(n * D + 1, dtype=torch.float32, device=Xd.device)
+    buf[1:].copy_(Xd.reshape(-1))
+    Xm = buf[1:].view(n, D)
+    assert Xm.data_ptr() % 16 != 0
+    O2, n22 = saq.project(plan, Xm)
+    torch.cuda.synchronize()
+    assert torch.equal(O, O2) and torch.equal(n2, n22)
+    x64 = X.astype(np.float64) - c.astype(np.float64)
+    ref = x64 @ M.astype(np.float64).T
+    nref = (x64 ** 2).sum(1)
+    err = np.abs(O.cpu().numpy()[:, :D] - ref)
+    assert np.all(err <= D * 2.0 ** -24 * np.sqrt(nref)[:, None])
+    # FP64 sums in another order, one FP32 rounding
+    assert np.all(np.abs(n2.cpu().numpy() - nref) <= 2.0 ** -24 * nref * (1 + 1e-9))
