@@ -173,6 +173,10 @@ __device__ __forceinline__ void gemm_split_tile_impl(
     // this thread copies B chunks t, t + 256, t + 512 of every k-step
     const u32x4* msrc = Ms + int64_t(tile_n) * ksteps * SCB + t;
     const float* crow = cp;
+    // the plan's c as constant memory: scalar loads also when the pointer
+    // comes from a grouped launch's argument struct
+    typedef const __attribute__((address_space(4))) float cfloat;
+    cfloat* ccp = (cfloat*)(cp);
     bool ref_bad = false;
     if (REF) {
         const int32_t id = R.ids != nullptr ? R.ids[arow_ok ? arow : n - 1] : 0;
@@ -217,8 +221,9 @@ __device__ __forceinline__ void gemm_split_tile_impl(
             float ra[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                // the plan's c is zero padded to k_pad: one uniform address
-                const float c = REF ? g.c[e] : cp[kb + e];
+                // the plan's c is zero padded to k_pad: one uniform address,
+                // read as constant memory (scalar loads)
+                const float c = REF ? g.c[e] : ccp[kb + e];
                 ra[e] = g.x[e] - c;
                 if (NORM) {
                     // exact (x - c)^2 in FP64; padding entries are 0 - 0
