@@ -91,37 +91,41 @@ __device__ __forceinline__ void store_quad(float* __restrict__ O, int64_t ld, in
 }
 
 // ---------------------------------------------------------------------------
-// Split-operand projection.  Every FP32 operand a is
-// written exactly as a0 + a1 + a2 in bf16 (RNE to 8 significant bits, then
-// RNE of the exact remainder, twice), and a b as the six products a_i b_j
-// with i + j <= 2, the bf16x6 scheme of Henry, Tang and Heinecke (2019).  The
-// three dropped products are below 2^-24 |a b| together, the size of one FP32
-// rounding, and the MFMAs (v_mfma_f32_32x32x16_bf16) accumulate in FP32, so
-// o keeps FP32 accuracy; the bf16 matrix rate is 16x the FP32 one, so the six
-// products take 3/8 of the FP32 MFMA time.  With ACC64 each 32-wide k-tile
-// (two k-steps) is accumulated in FP32 from zero and then added into FP64
-// totals, so the FP32 rounding error grows with the tile length (32) rather
-// than with D.
+// Split-operand projection.  Every FP32 operand a is written exactly as
+// a0 + a1 + a2 in bf16 (RNE to 8 significant bits, then RNE of the exact
+// remainder, twice), and a b as the six products a_i b_j with i + j <= 2, the
+// bf16x6 scheme of Henry, Tang and Heinecke (2019).  The three dropped
+// products are below 2^-24 |a b| together, the size of one FP32 rounding, and
+// the MFMAs (v_mfma_f32_32x32x16_bf16) accumulate in FP32, so o keeps FP32
+// accuracy; the bf16 matrix rate is 16x the FP32 one, so the six products
+// take 3/8 of the FP32 MFMA time.  With ACC64 each 32-wide k-tile (two
+// k-steps) is accumulated in FP32 from zero and then added into FP64 totals,
+// so the FP32 rounding error grows with the tile length (32) rather than
+// with D.
 //
-// Tile (64 BI) x 128, k-step 16, four waves of (32 BI) x 64 (BI x 2 blocks
-// of 32 x 32); BI = 2 for FP32 accumulation, 1 for FP64 totals and in
-// grouped launches that also carry FP64-total datasets.  Every output element
-// sees the same MFMA sequence over k in both shapes, so they give identical
-// results.  Per
-// buffer, LDS holds both operands as 16-byte chunks [A|B][term][k half]
+// Tile (64 BI) x 128, k-step 16, four waves of (32 BI) x 64 (BI x 2 blocks of
+// 32 x 32); BI = 2 for FP32 accumulation, 1 for FP64 totals and in grouped
+// launches that also carry FP64-total datasets.  Every output element sees
+// the same MFMA sequence over k in both shapes, so they give identical
+// results.
+//
+// Per buffer, LDS holds both operands as 16-byte chunks [A|B][term][k half]
 // [row]: a lane's MFMA operand (8 bf16 of one row, k half = lane / 32) is one
 // chunk, and a wave reads two contiguous 512-byte runs.  The X rows are split
-// as they are staged, thread t taking row t % (64 BI) and k half
-// t / (64 BI), so a wave writes 64 consecutive chunks; M comes pre-split
-// from the plan in the same chunk order, one 16-byte copy per chunk.  A
-// k-step has only 24 MFMAs per wave (768 cycles), too short to cover a
+// as they are staged, thread t taking row t % (64 BI) and k half t / (64 BI),
+// so a wave writes 64 consecutive chunks; M comes pre-split from the plan in
+// the same chunk order, one 16-byte copy per chunk.
+//
+// A k-step has only 24 MFMAs per wave (768 cycles), too short to cover a
 // global load, so X and the B chunks are loaded two k-steps ahead into
 // alternating register sets.  The bulk of the k-steps runs in a loop whose
-// loads are all full-width and unconditional: after the ragged-tail branch
+// loads are all full-width and unconditional: behind the ragged-tail branch
 // the compiler can no longer count the loads in flight, and its wait before
-// each A-tile store then also covered the loads issued for two steps ahead.  For BI = 2, 48 KB of LDS and at most 168 VGPRs
-// give three workgroups per compute unit (two with per-row references,
-// whose extra c registers would spill at three); FP64 totals run two.
+// each A-tile store then also covered the loads issued two steps ahead.
+//
+// For BI = 2, 48 KB of LDS and at most 168 VGPRs give three workgroups per
+// compute unit (two with per-row references, whose extra c registers would
+// spill at three); FP64 totals run two.
 // ---------------------------------------------------------------------------
 constexpr int SK = saq::kSplitK;              // input dims per k-step
 constexpr int SCB = saq::kSplitChunks;        // B chunks per buffer
@@ -358,7 +362,7 @@ __device__ __forceinline__ void gemm_tile(
     float* __restrict__ norm2, int tile_m, int tile_n, float* __restrict__ lds, RefRows R) {
     // the wave's second 32-column block (wave w covers columns
     // 64 (w % 2) .. 64 (w % 2) + 63 of the tile) holds kept dims
-    const bool fullb = tile_n * TN + 64 * ((threadIdx.x >> 6) & 1) + 32 < dk;
+    const bool fullb = tile_n * TN + 64 * int((threadIdx.x >> 6) & 1) + 32 < dk;
     if (norm2 != nullptr && tile_n == 0)
         gemm_split_tile_impl<LAYOUT, true, BI, true, REF, ACC64>(vec, X, n, D, Ms, k_pad, cp, dk,
                                                                  O, ld, norm2, tile_m, tile_n, lds, R);
