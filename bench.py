@@ -103,8 +103,9 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {a.gpus} is not supported "
-              "(encoding shards by vectors with no exchange; see the design notes)",
+        print(f"bench.py: measures one GPU; --gpus {a.gpus} is not supported. The encode "
+              "shards by vectors with no exchange between GPUs (each holds the plan and "
+              "encodes its own rows), so N GPUs run at N times one GPU's rate.",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -47,7 +47,7 @@ typedef enum {
     SAQ_EINVAL = 1,        /* bad argument */
     SAQ_ENOMEM = 2,        /* host allocation failed */
     SAQ_EDEVICE = 3,       /* HIP error (launch, copy) */
-    SAQ_EUNSUPPORTED = 4,  /* valid but not supported by this build */
+    SAQ_EUNSUPPORTED = 4,  /* valid but not supported by this library */
     SAQ_EIO = 5            /* plan file missing, truncated or corrupt */
 } saq_status;
 

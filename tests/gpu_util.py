@@ -59,7 +59,7 @@ U32 = 2.0 ** -24
 
 def compare(plan, packed, fac, ref, max_rate=1e-4, factor_rtol=1e-5, label="",
             projected_input=False):
-    """Spec bar: >= 99.99 % identical codes, every difference exactly
+    """The parity bar: >= 99.99 % identical codes, every difference exactly
     1; factors within 1e-5 relative where the segment's codes agree (else
     against the oracle's factor recomputed on the GPU's codes); the stored
     norm within 1e-6 relative.  Returns the mismatch rate.

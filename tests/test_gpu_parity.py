@@ -1,10 +1,10 @@
 """Device path vs the FP64 oracle, through the C ABI (libsaq.so).
 
-Tolerances (the benchmark spec): >= 99.99 % identical codes with every difference
-exactly 1, rescale factors within 1e-5 relative, mean relative distance
-error within 1 % of the oracle's.  The projection is an FP32 GEMM, so its
-elementwise error bound is the classical K u sum|x_k m_k| <= K u ||x - c||
-(u = 2^-24, ||m_j|| = 1)."""
+Tolerances: >= 99.99 % identical codes with every difference exactly 1,
+rescale factors within 1e-5 relative, mean relative distance error within
+1 % of the oracle's.  The projection computes each product to FP32 accuracy
+and accumulates in FP32, so its elementwise error bound is the classical
+K u sum|x_k m_k| <= K u ||x - c|| (u = 2^-24, ||m_j|| = 1)."""
 import numpy as np
 import pytest
 
@@ -202,8 +202,8 @@ def test_estimate_dist(cfg1):
 def test_estimate_dist_shapes():
     """The estimate scan's tiles (128 records x 64 queries x 32 dims) on ragged
     shapes: query counts around 32 (one query block below it) and 64, record
-    counts around 128, segment widths
-    that are not multiples of 32 (down to 3) and 1- to 16-bit segments; the
+    counts around 128, segment widths that are not multiples of 32 (down
+    to 3) and 1- to 16-bit segments; the
     result equals the oracle's estimator on the same records (FP32
     accumulation tolerance)."""
     rng = np.random.default_rng(7)
