@@ -47,6 +47,11 @@ enum { LAYOUT_ROWS = 0, LAYOUT_DIMS = 1, LAYOUT_TILES = 2 };
 // Tile order is XCD-aware: workgroup b runs on XCD b % 8; XCD x walks row
 // tiles x, x+8, ... and, inside each, all column tiles back to back, so the
 // X tile is fetched from HBM once per XCD and re-read from that XCD's L2.
+// When the pre-split M is larger than one L2 but half of it fits, each half
+// of the XCDs takes half of the column tiles instead (the projection kernel's
+// `halves` order): every workgroup streams its column tile's M, and M then
+// stays in L2 (the fetch per launch at 1M x 960 drops from 26-28 GB to 16 GB
+// at the same speed).
 // ---------------------------------------------------------------------------
 template <int BI> constexpr int gemm_rows() { return 64 * BI; }
 
@@ -383,13 +388,36 @@ template <bool VEC, int LAYOUT, bool ACC64, bool REF>
 __global__ __launch_bounds__(256, (ACC64 || REF) ? 2 : 3) void project_kernel(
     const float* __restrict__ X, int64_t n, int D, const u32x4* __restrict__ Ms, int k_pad, const float* __restrict__ cp, int dk,
     float* __restrict__ O, int64_t ld, float* __restrict__ norm2, int tiles_m, int tiles_n,
-    RefRows R) {
+    RefRows R, int halves) {
     constexpr int BI = gemm_bi<ACC64>();
     __shared__ __attribute__((aligned(16))) float lds[gemm_lds_size<ACC64>()];
     const int bid = blockIdx.x;
     const int xcd = bid % NXCD, local = bid / NXCD;
-    const int tile_n = local % tiles_n;
-    const int tile_m = (local / tiles_n) * NXCD + xcd;
+    int tile_n, tile_m;
+    if (!halves) {
+        tile_n = local % tiles_n;
+        tile_m = (local / tiles_n) * NXCD + xcd;
+    } else {
+        // each half of the XCDs takes half of the column tiles (the middle one
+        // of an odd count split by row tiles), so each XCD's L2 holds half of
+        // the pre-split M; inside a half, XCD xi walks row tiles xi, xi+4, ...
+        // with the half's column tiles back to back, then its share of the
+        // middle column tile
+        const int g = xcd / (NXCD / 2), xi = xcd % (NXCD / 2);
+        const int cm = tiles_n / 2, odd = tiles_n & 1, hm = (tiles_m + 1) / 2;
+        const int c0 = g == 0 ? 0 : cm + odd, nc = g == 0 ? cm : tiles_n - cm - odd;
+        const int rows = (tiles_m - xi + NXCD / 2 - 1) / (NXCD / 2);   // row tiles xi, xi+4, ...
+        if (local < nc * rows) {
+            tile_n = c0 + local % nc;
+            tile_m = (local / nc) * (NXCD / 2) + xi;
+        } else {
+            if (!odd) return;
+            const int r0 = g == 0 ? 0 : hm, r1 = g == 0 ? hm : tiles_m;
+            tile_n = cm;
+            tile_m = r0 + (local - nc * rows) * (NXCD / 2) + xi;
+            if (tile_m >= r1) return;
+        }
+    }
     if (tile_m >= tiles_m) return;
     gemm_tile<LAYOUT, ACC64, BI, REF>(VEC, X, n, D, Ms, k_pad, cp, dk, O, ld, norm2, tile_m, tile_n,
                                       lds, R);
@@ -1133,8 +1161,20 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
     const int rows = p->acc64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
     const int tiles_m = int((n + rows - 1) / rows);
     const int tiles_n = p->layout.n_pad / TN;
-    const int slots = (tiles_m + NXCD - 1) / NXCD;
-    const dim3 grid(unsigned(NXCD * slots * tiles_n));
+    // two halves of the XCDs when the pre-split M is larger than one L2 (4 MB)
+    // and half of it fits
+    const int64_t ms_bytes = int64_t(tiles_n) * (p->layout.k_pad / SK) * SCB * 16;
+    const int halves = (tiles_n >= 2 && ms_bytes > (int64_t(4) << 20) && ms_bytes <= (int64_t(7) << 20)) ? 1 : 0;
+    int64_t slots;
+    if (!halves) {
+        slots = int64_t((tiles_m + NXCD - 1) / NXCD) * tiles_n;
+    } else {
+        const int cm = tiles_n / 2, odd = tiles_n & 1;
+        const int64_t rows = (tiles_m + NXCD / 2 - 1) / (NXCD / 2);
+        const int64_t rows_mid = ((tiles_m + 1) / 2 + NXCD / 2 - 1) / (NXCD / 2);
+        slots = rows * std::max(cm, tiles_n - cm - odd) + (odd ? rows_mid : 0);
+    }
+    const dim3 grid(unsigned(NXCD * slots));
     const bool vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0) &&
                      ((reinterpret_cast<uintptr_t>(R.refs) & 15) == 0);
     if (layout == LAYOUT_DIMS && ((reinterpret_cast<uintptr_t>(O) & 15) != 0 || (ld % 4) != 0))
@@ -1143,7 +1183,8 @@ saq_status launch_project(const saq_plan* p, const float* X, int64_t n, float* O
         return saq::fail(SAQ_EINVAL, "tiled output needs a 16-byte aligned buffer");
 #define SAQ_LAUNCH_PROJ(V, L, A, F)                                                               \
     hipLaunchKernelGGL((project_kernel<V, L, A, F>), grid, dim3(256), 0, st, X, n, p->D, dev_Ms(p),\
-                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R)
+                       p->layout.k_pad, dev_c(p), p->D_kept, O, ld, norm2, tiles_m, tiles_n, R,  \
+                       halves)
 #define SAQ_LAUNCH_PROJ2(V, L, F) \
     do { if (p->acc64) SAQ_LAUNCH_PROJ(V, L, true, F); else SAQ_LAUNCH_PROJ(V, L, false, F); } while (0)
     // references per row exist for the tiled (encode) and row (query) layouts
