@@ -35,19 +35,38 @@ VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock: lane-ops/s
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "encode_1Mx960_b4_hbm_counters.md")
 
 
+def kernel_code_digest() -> str:
+    """sha256 of the encode kernels' code: csrc/device.hip followed by
+    csrc/plan.hpp with comments removed, every run of blanks in a line made
+    one space and empty lines dropped, so that an edit of comments or of
+    indentation keeps the digest and a change of code changes it."""
+    return code_digest("\n".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f)).read()
+                                  for f in ("device.hip", "plan.hpp")))
+
+
+def code_digest(src: str) -> str:
+    """sha256 of C++ source text with comments removed (string and character
+    literals kept as written), blanks in a line collapsed and empty lines
+    dropped."""
+    import hashlib
+    import re
+    lexeme = re.compile(r'("(?:\\.|[^"\\\n])*"|\'(?:\\.|[^\'\\\n])*\')|//[^\n]*|/\*.*?\*/', re.S)
+    code = lexeme.sub(lambda m: m.group(1) if m.group(1) else " ", src)
+    lines = (" ".join(line.split()) for line in code.splitlines())
+    return hashlib.sha256("\n".join(x for x in lines if x).encode()).hexdigest()
+
+
 def _record(path: str, tag: str, workload: str):
     """The machine-readable record of a committed counter summary, or None
-    when it is for another workload or for other kernel sources than the
-    ones built here."""
-    import hashlib
+    when it is for another workload or for other kernel code than the code
+    built here."""
     try:
         text = open(path).read()
         rec = json.loads(text.split(f"<!-- {tag} ", 1)[1].split(" -->", 1)[0])
-        src = b"".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f), "rb").read()
-                       for f in ("device.hip", "plan.hpp"))
+        digest = kernel_code_digest()
     except (OSError, IndexError, ValueError):
         return None
-    if rec.get("workload") != workload or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if rec.get("workload") != workload or digest != rec.get("code_sha256"):
         return None
     return rec
 

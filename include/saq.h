@@ -68,7 +68,8 @@ typedef struct {
                                          2: FP32 per 32-wide k-tile, FP64 across tiles.  Every
                                          FP32 product is formed as six bf16 matrix-core
                                          products of operands split exactly into three bf16
-                                         terms (error below one FP32 rounding). */
+                                         terms (each product within about two FP32
+                                         unit roundoffs, 2^-23 relative). */
 } saq_plan_params;
 
 typedef struct {

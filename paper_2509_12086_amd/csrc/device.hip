@@ -99,8 +99,9 @@ __device__ __forceinline__ void store_quad(float* __restrict__ O, int64_t ld, in
 // Split-operand projection.  Every FP32 operand a is written exactly as
 // a0 + a1 + a2 in bf16 (RNE to 8 significant bits, then RNE of the exact
 // remainder, twice), and a b as the six products a_i b_j with i + j <= 2, the
-// bf16x6 scheme of Henry, Tang and Heinecke (2019).  The three dropped
-// products are below 2^-24 |a b| together, the size of one FP32 rounding, and
+// bf16x6 scheme of Henry, Tang and Heinecke (2019).  Since |a1| <= 2^-8 |a|
+// and |a2| <= 2^-16 |a|, the three dropped products (a1 b2, a2 b1, a2 b2) are
+// below (2^-23 + 2^-32) |a b| together, about two FP32 unit roundoffs, and
 // the MFMAs (v_mfma_f32_32x32x16_bf16) accumulate in FP32, so o keeps FP32
 // accuracy; the bf16 matrix rate is 16x the FP32 one, so the six products
 // take 3/8 of the FP32 MFMA time.  With ACC64 each 32-wide k-tile (two

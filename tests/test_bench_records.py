@@ -1,0 +1,46 @@
+"""The benchmark's link to its committed counter records (no GPU needed).
+
+`roofline.traffic` and the VALU figures come from rocprofv3 counter runs kept
+as text under profiles/.  They are reported only while the kernel code is the
+code the counters were taken on, keyed by a digest of the code with comments
+and blanks removed: an edit of comments must keep the digest, any edit of code
+must change it."""
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DEVICE = os.path.join(ROOT, "paper_2509_12086_amd", "csrc", "device.hip")
+
+
+def test_comment_and_blank_edits_keep_the_digest():
+    src = open(DEVICE).read()
+    base = bench.code_digest(src)
+    assert bench.code_digest("// a new first line\n" + src) == base
+    assert bench.code_digest(src.replace("\n", "\n\n")) == base
+    assert bench.code_digest(src.replace("    ", "\t")) == base
+    assert bench.code_digest(src + "\n/* a block comment\n   over two lines */\n") == base
+    # a comment reflowed over more lines
+    assert bench.code_digest("int a; // one two three\n") == bench.code_digest("int a; // one\n// two three\n")
+
+
+def test_code_edits_change_the_digest():
+    src = open(DEVICE).read()
+    base = bench.code_digest(src)
+    assert "SK" in src
+    assert bench.code_digest(src.replace("SK", "SK2", 1)) != base
+    assert bench.code_digest(src + "\nstatic int unused_probe;\n") != base
+    # comment markers inside literals are code, not comments
+    assert bench.code_digest('const char* s = "a // b";\n') != bench.code_digest('const char* s = "a ";\n')
+    assert bench.code_digest("char c = '/'; int d; // x\n") != bench.code_digest("char c = '*'; int d;\n")
+    # line structure is kept (a preprocessor line must not absorb the next)
+    assert bench.code_digest("#define A 1\nint b;\n") != bench.code_digest("#define A 1 int b;\n")
+
+
+def test_records_are_keyed_by_the_code_digest():
+    """Each committed record carries a code digest; a record for another
+    digest or another workload is not reported."""
+    for path, tag in ((bench.TRAFFIC_RECORD, "traffic-record"), (bench.INSTR_RECORD, "instruction-record")):
+        text = open(path).read()
+        assert f"<!-- {tag} " in text and '"code_sha256": "' in text
+        assert bench._record(path, tag, "another workload") is None

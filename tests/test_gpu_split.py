@@ -100,9 +100,13 @@ def test_projection_k_loop_boundaries(D, bits):
     and the ragged end through element loads.  Input dimensions around those
     boundaries (no bulk trips below 48, a ragged 16-byte tail at 100, odd D),
     FP32 accumulation (4-bit segment) and FP64 k-tile totals (8-bit): the
-    projection stays within the FP32 dot-product bound of the FP64 one, the
-    norm is the FP64 ||x - c||^2 rounded once, and a misaligned copy of the
-    same rows (element loads only) gives the same bits."""
+    projection stays within D FP32 unit roundoffs (2^-24) of ||x - c|| of the
+    FP64 one, the norm is the FP64 ||x - c||^2 rounded once, and a misaligned
+    copy of the same rows (element loads only) gives the same bits.  The
+    bound holds for D >= 16 with room: one rounding of x - c, the split's
+    dropped products (below 2^-23 relative) and six accumulator roundings
+    per 16-wide k-step, each at most u times a sum bounded by ||x - c||
+    (the rows of M are orthonormal)."""
     rng = np.random.default_rng(10 * D + bits)
     n = 333
     X = (rng.standard_normal((n, D)) * 3.0 + 5.0).astype(np.float32)
