@@ -40,7 +40,8 @@ def kernel_code_digest() -> str:
     csrc/plan.hpp with comments removed, every run of blanks in a line made
     one space and empty lines dropped, so that an edit of comments or of
     indentation keeps the digest and a change of code changes it."""
-    return code_digest("\n".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f)).read()
+    return code_digest("\n".join(open(os.path.join(ROOT, "paper_2509_12086_amd", "csrc", f),
+                                       encoding="utf-8").read()
                                   for f in ("device.hip", "plan.hpp")))
 
 
@@ -61,7 +62,7 @@ def _record(path: str, tag: str, workload: str):
     when it is for another workload or for other kernel code than the code
     built here."""
     try:
-        text = open(path).read()
+        text = open(path, encoding="utf-8").read()
         rec = json.loads(text.split(f"<!-- {tag} ", 1)[1].split(" -->", 1)[0])
         digest = kernel_code_digest()
     except (OSError, IndexError, ValueError):
