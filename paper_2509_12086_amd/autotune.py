@@ -48,7 +48,7 @@ def tune(entries, rounds: int = 4, reps: int = 2, sample_rows: int = 131072,
     if sig in _CACHE:
         return _CACHE[sig], []
     if cache_file and os.path.exists(cache_file):
-        stored = json.load(open(cache_file))
+        stored = _read_cache(cache_file)
         if sig in stored:
             _CACHE[sig] = BatchTuning(**stored[sig])
             return _CACHE[sig], []
@@ -75,7 +75,13 @@ def tune(entries, rounds: int = 4, reps: int = 2, sample_rows: int = 131072,
     best = min(table, key=lambda r: r[1])[0]
     _CACHE[sig] = best
     if cache_file:
-        stored = json.load(open(cache_file)) if os.path.exists(cache_file) else {}
+        stored = _read_cache(cache_file) if os.path.exists(cache_file) else {}
         stored[sig] = {"quant_waves": best.quant_waves, "gemm_xcd_order": best.gemm_xcd_order}
-        json.dump(stored, open(cache_file, "w"))
+        with open(cache_file, "w", encoding="utf-8") as f:
+            json.dump(stored, f)
     return best, table
+
+
+def _read_cache(path: str) -> dict:
+    with open(path, encoding="utf-8") as f:
+        return json.load(f)

@@ -14,7 +14,7 @@ DEVICE = os.path.join(ROOT, "paper_2509_12086_amd", "csrc", "device.hip")
 
 
 def test_comment_and_blank_edits_keep_the_digest():
-    src = open(DEVICE).read()
+    src = open(DEVICE, encoding="utf-8").read()
     base = bench.code_digest(src)
     assert bench.code_digest("// a new first line\n" + src) == base
     assert bench.code_digest(src.replace("\n", "\n\n")) == base
@@ -25,7 +25,7 @@ def test_comment_and_blank_edits_keep_the_digest():
 
 
 def test_code_edits_change_the_digest():
-    src = open(DEVICE).read()
+    src = open(DEVICE, encoding="utf-8").read()
     base = bench.code_digest(src)
     assert "SK" in src
     assert bench.code_digest(src.replace("SK", "SK2", 1)) != base
@@ -41,6 +41,6 @@ def test_records_are_keyed_by_the_code_digest():
     """Each committed record carries a code digest; a record for another
     digest or another workload is not reported."""
     for path, tag in ((bench.TRAFFIC_RECORD, "traffic-record"), (bench.INSTR_RECORD, "instruction-record")):
-        text = open(path).read()
+        text = open(path, encoding="utf-8").read()
         assert f"<!-- {tag} " in text and '"code_sha256": "' in text
         assert bench._record(path, tag, "another workload") is None
