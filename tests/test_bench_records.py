@@ -1,4 +1,5 @@
-"""The benchmark's link to its committed counter records (no GPU needed).
+"""Host side of the benchmark (no GPU needed): its one-GPU contract and its
+link to the committed counter records.
 
 `roofline.traffic` and the VALU figures come from rocprofv3 counter runs kept
 as text under profiles/.  They are reported only while the kernel code is the
@@ -6,6 +7,8 @@ code the counters were taken on, keyed by a digest of the code with comments
 and blanks removed: an edit of comments must keep the digest, any edit of code
 must change it."""
 import os
+import subprocess
+import sys
 
 import bench
 
@@ -44,3 +47,14 @@ def test_records_are_keyed_by_the_code_digest():
         text = open(path, encoding="utf-8").read()
         assert f"<!-- {tag} " in text and '"code_sha256": "' in text
         assert bench._record(path, tag, "another workload") is None
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    """The benchmark measures one GPU: --gpus N > 1 exits with status 2 and a
+    message on stderr, before touching a GPU, and prints no result line."""
+    for n in (2, 8):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                           capture_output=True, text=True, timeout=60)
+        assert r.returncode == 2
+        assert f"--gpus {n} is not supported" in r.stderr
+        assert r.stdout == ""
