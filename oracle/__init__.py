@@ -52,23 +52,30 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        i64, i32 = ctypes.c_int64, ctypes.c_int32
-        L.saqo_quantize.argtypes = [P, i64, i32, i32, P, P, i32, P, P, P, P, P, ctypes.c_int]
-        L.saqo_project.argtypes = [P, i64, i32, P, i32, P, P, P, ctypes.c_int]
-        L.saqo_encode.argtypes = [P, i64, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P, P,
-                                  ctypes.c_int]
-        L.saqo_pack.argtypes = [P, i64, i32, i32, P, P, P, i64]
-        L.saqo_estimate.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64, i32, P,
-                                    ctypes.c_int]
-        L.saqo_estimate_multistage.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64,
-                                               P, P, ctypes.c_double, P, P, P, P, ctypes.c_int]
-        for f in ("saqo_quantize", "saqo_project", "saqo_encode", "saqo_pack", "saqo_estimate",
-                  "saqo_estimate_multistage"):
-            getattr(L, f).restype = ctypes.c_int
-        _lib = L
+        _lib = load(_LIB)
     return _lib
+
+
+def load(path: str):
+    """ctypes handle on a compiled oracle library at `path` (the oracle's own
+    build, or a copy with a planted mistake that a test compiled to check
+    that the pins catch it)."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i64, i32 = ctypes.c_int64, ctypes.c_int32
+    L.saqo_quantize.argtypes = [P, i64, i32, i32, P, P, i32, P, P, P, P, P, ctypes.c_int]
+    L.saqo_project.argtypes = [P, i64, i32, P, i32, P, P, P, ctypes.c_int]
+    L.saqo_encode.argtypes = [P, i64, i32, P, i32, P, i32, P, P, i32, P, P, P, P, P, P, P,
+                              ctypes.c_int]
+    L.saqo_pack.argtypes = [P, i64, i32, i32, P, P, P, i64]
+    L.saqo_estimate.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64, i32, P,
+                                ctypes.c_int]
+    L.saqo_estimate_multistage.argtypes = [P, i32, i32, P, i32, P, i32, P, P, P, P, P, i64,
+                                           P, P, ctypes.c_double, P, P, P, P, ctypes.c_int]
+    for f in ("saqo_quantize", "saqo_project", "saqo_encode", "saqo_pack", "saqo_estimate",
+              "saqo_estimate_multistage"):
+        getattr(L, f).restype = ctypes.c_int
+    return L
 
 
 def _p(a: Optional[np.ndarray]):
@@ -97,9 +104,10 @@ def _kept(widths: Sequence[int], bits: Sequence[int]):
 
 
 def quantize(O: np.ndarray, widths: Sequence[int], bits: Sequence[int], rounds: int,
-             instrument: bool = False, threads: int = 0) -> Encoded:
+             instrument: bool = False, threads: int = 0, library=None) -> Encoded:
     """Quantize projected rows O [n, Dk] (float64) segment by segment.
-    ``widths``/``bits`` list the kept segments (bits > 0) in plan order."""
+    ``widths``/``bits`` list the kept segments (bits > 0) in plan order.
+    ``library`` (from ``load``) replaces the oracle's own build."""
     O = np.ascontiguousarray(O, np.float64)
     n, dk = O.shape
     w, b = _kept(widths, bits)
@@ -109,8 +117,8 @@ def quantize(O: np.ndarray, widths: Sequence[int], bits: Sequence[int], rounds: 
     sa = np.zeros((n, k, 4)) if instrument else None
     ca = np.zeros((n, dk, 2)) if instrument else None
     rs = np.zeros((n, k, MAX_ROUNDS + 1), np.int32) if instrument else None
-    rc = lib().saqo_quantize(_p(O), n, dk, k, _p(w), _p(b), rounds, _p(codes), _p(fac),
-                             _p(sa), _p(ca), _p(rs), threads)
+    rc = (library or lib()).saqo_quantize(_p(O), n, dk, k, _p(w), _p(b), rounds, _p(codes),
+                                          _p(fac), _p(sa), _p(ca), _p(rs), threads)
     if rc:
         raise ValueError("oracle quantize: bad arguments")
     return Encoded(codes, fac, None, O, sa, ca, rs)
