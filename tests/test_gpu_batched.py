@@ -7,7 +7,7 @@ import pytest
 import synth
 import paper_2509_12086_amd as saq
 from paper_2509_12086_amd import autotune
-from gpu_util import compare, cuda, oracle_encode, say, to_dev
+from gpu_util import compare, cuda, gpu_project, oracle_encode, say, to_dev
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -84,8 +84,9 @@ def test_batched_matches_oracle_wide_segments(batch):
     outs = saq.encode_batched([(p, X)], 4)
     torch.cuda.synchronize()
     c, f = outs[0]
-    compare(p, c.cpu().numpy(), f.cpu().numpy(), oracle_encode(p, X.cpu().numpy(), 4),
-            label="batched D3072 b8")
+    Xh = X.cpu().numpy()
+    compare(p, c.cpu().numpy(), f.cpu().numpy(), oracle_encode(p, Xh, 4),
+            label="batched D3072 b8", dev_O=gpu_project(p, Xh))
 
 
 def test_batched_argument_errors(batch):
@@ -148,6 +149,6 @@ def test_cfg3_full_size_batched_sampled():
     for (p, X), (c, f) in zip(entries, outs):
         Xs = X[ti].cpu().numpy()
         compare(p, c[ti].cpu().numpy(), f[ti].cpu().numpy(), oracle_encode(p, Xs, 4),
-                label=f"cfg3 D3072 {p.code_bytes * 8 // 3072} b/dim")
+                label=f"cfg3 D3072 {p.code_bytes * 8 // 3072} b/dim", dev_O=gpu_project(p, Xs))
     del entries, outs
     torch.cuda.empty_cache()

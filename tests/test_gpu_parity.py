@@ -11,8 +11,8 @@ import pytest
 import oracle
 import synth
 import paper_2509_12086_amd as saq
-from gpu_util import (compare, cuda, gpu_encode, oracle_encode, oracle_records, oracle_scan,
-                      say, to_dev)
+from gpu_util import (compare, cuda, gpu_encode, gpu_project, oracle_encode, oracle_records,
+                      oracle_scan, say, to_dev)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -117,7 +117,7 @@ def test_encode_cfg1_end_to_end(cfg1):
     say("encode cfg1 10000 x 128, 4 b/dim, r=4")
     packed, fac = gpu_encode(plan, X, 4)
     ref = oracle_encode(plan, X, 4)
-    compare(plan, packed, fac, ref, label="cfg1")
+    compare(plan, packed, fac, ref, label="cfg1", dev_O=gpu_project(plan, X))
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 127, 129, 1000])
@@ -126,7 +126,8 @@ def test_encode_ragged_sizes(cfg1, n):
     say(f"encode ragged n={n}")
     Xs = X[1000:1000 + n]
     packed, fac = gpu_encode(plan, Xs, 4)
-    compare(plan, packed, fac, oracle_encode(plan, Xs, 4), label=f"n={n}")
+    compare(plan, packed, fac, oracle_encode(plan, Xs, 4), label=f"n={n}",
+            dev_O=gpu_project(plan, Xs))
     # the records of a slice equal the rows of a bigger batch (no cross-talk)
     big, bigf = gpu_encode(plan, X[990:1000 + n + 10], 4)
     assert np.array_equal(big[10:10 + n], packed) and np.array_equal(bigf[10:10 + n], fac)
@@ -142,7 +143,7 @@ def test_encode_degenerate_rows(cfg1):
     say("encode degenerate rows")
     packed, fac = gpu_encode(plan, Xs, 4)
     ref = oracle_encode(plan, Xs, 4)
-    compare(plan, packed, fac, ref, label="degenerate")
+    compare(plan, packed, fac, ref, label="degenerate", dev_O=gpu_project(plan, Xs))
     codes = saq.unpack_codes(plan, packed)
     assert np.all(fac[0, :-1] == 0.0)
     assert np.array_equal(packed[1], packed[2])
@@ -159,7 +160,8 @@ def test_encode_non_multiple_dims_and_rounds():
     for rounds in (0, 1, 8):
         say(f"encode D=99 rounds={rounds}")
         packed, fac = gpu_encode(plan, X, rounds)
-        compare(plan, packed, fac, oracle_encode(plan, X, rounds), label=f"D99 r={rounds}")
+        compare(plan, packed, fac, oracle_encode(plan, X, rounds), label=f"D99 r={rounds}",
+                dev_O=gpu_project(plan, X))
 
 
 def test_encode_deterministic(cfg1):
@@ -283,7 +285,11 @@ def test_device_argument_errors(cfg1):
 @pytest.mark.parametrize("bpd", [4.0, 2.0])
 def test_cfg2_full_size_sampled(bpd):
     """1M x 960 cluster mixture at 2 and 4 b/dim, encoded in the single launch
-    pair the benchmark times; 3000 sampled records compared with the oracle."""
+    pair the benchmark times; 3000 sampled records compared with the oracle,
+    and the mean relative error of estimated squared distances (Section 3.2
+    estimator, Section 5's metric) between 100 held-out queries and those
+    records, device-encoded and device-scanned, within 1 % of the oracle's
+    records' under the oracle's estimator."""
     ds = synth.cfg2()
     say(f"cfg2 full size bpd={bpd}: generating 1M x 960 on the device")
     X = ds.rows_torch(ds.n, cuda())
@@ -297,7 +303,20 @@ def test_cfg2_full_size_sampled(bpd):
     Xs = X[it].cpu().numpy()
     packed, f = codes[it].cpu().numpy(), fac[it].cpu().numpy()
     del X, codes, fac
-    compare(plan, packed, f, oracle_encode(plan, Xs, 4), label=f"cfg2 bpd={bpd}")
+    ref = oracle_encode(plan, Xs, 4)
+    compare(plan, packed, f, ref, label=f"cfg2 bpd={bpd}", dev_O=gpu_project(plan, Xs))
+    Qr = ds.queries(100)
+    d2 = saq.estimate_dist(plan, to_dev(Qr), to_dev(packed), to_dev(f))
+    torch.cuda.synchronize()
+    M, c, _ = plan.arrays()
+    true = oracle.true_dist2(Qr, Xs)
+    ref_d2 = oracle.estimate(Qr, M, c, plan.kept_widths, plan.kept_bits, ref.codes,
+                             ref.factors, ref.norm2)
+    e_gpu = float(oracle.relative_error(d2.cpu().numpy(), true).mean())
+    e_orc = float(oracle.relative_error(ref_d2, true).mean())
+    say(f"  [cfg2 bpd={bpd}] mean relative distance error: device {e_gpu:.5e}, "
+        f"oracle {e_orc:.5e} ({abs(e_gpu - e_orc) / e_orc:.2e} apart, relative)")
+    assert abs(e_gpu - e_orc) <= 0.01 * e_orc
 
 
 def test_projection_accumulation_modes_agree_within_bounds():

@@ -13,7 +13,7 @@ import pytest
 import oracle
 import synth
 import paper_2509_12086_amd as saq
-from gpu_util import compare, cuda, say, to_dev
+from gpu_util import compare, cuda, gpu_project, say, to_dev
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -46,11 +46,15 @@ def _oracle_by_list(plan, X, refs, ids, rounds=4):
     fac = np.zeros((n, k))
     nn = np.zeros(n)
     O = np.zeros((n, dk))
+    sa = np.zeros((n, k, 4))
+    ca = np.zeros((n, dk, 2))
     for r in np.unique(ids):
         sel = np.nonzero(ids == r)[0]
-        e = oracle.encode(X[sel], M, refs[r], plan.kept_widths, plan.kept_bits, rounds)
+        e = oracle.encode(X[sel], M, refs[r], plan.kept_widths, plan.kept_bits, rounds,
+                          instrument=True)
         codes[sel], fac[sel], nn[sel], O[sel] = e.codes, e.factors, e.norm2, e.O
-    return oracle.Encoded(codes, fac, nn, O)
+        sa[sel], ca[sel] = e.seg_aux, e.code_aux
+    return oracle.Encoded(codes, fac, nn, O, sa, ca)
 
 
 def test_encode_with_references_matches_oracle(lists):
@@ -60,7 +64,8 @@ def test_encode_with_references_matches_oracle(lists):
     codes, fac = saq.encode(plan, to_dev(X), 4, refs=to_dev(refs), ref_ids=to_dev(ids))
     torch.cuda.synchronize()
     ref = _oracle_by_list(plan, X, refs, ids)
-    compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, label="ref lists")
+    compare(plan, codes.cpu().numpy(), fac.cpu().numpy(), ref, label="ref lists",
+            dev_O=gpu_project(plan, X - refs[ids]))
     # ragged n and every record on its list's reference, not the plan's c
     n = 777
     c2, f2 = saq.encode(plan, to_dev(X[:n]), 4, refs=to_dev(refs), ref_ids=to_dev(ids[:n]))
@@ -156,4 +161,5 @@ def test_full_size_reference_encode_sampled():
     Xs, ids_s = X[it].cpu().numpy(), ids[it].cpu().numpy()
     packed, f = codes[it].cpu().numpy(), fac[it].cpu().numpy()
     del X, codes, fac
-    compare(plan, packed, f, _oracle_by_list(plan, Xs, refs, ids_s), label="reference 1M")
+    compare(plan, packed, f, _oracle_by_list(plan, Xs, refs, ids_s), label="reference 1M",
+            dev_O=gpu_project(plan, Xs - refs[ids_s]))
