@@ -190,6 +190,24 @@ saq_status saq_encode_ref(const saq_plan* plan, const float* X_dev, int64_t n,
                           int32_t rounds, uint8_t* codes_dev, float* factors_dev, void* ws_dev,
                           int64_t ws_bytes, void* stream);
 
+/* saq_encode for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   the same kernels and records as saq_encode, with the workspace taken from
+   a fixed device array of SAQ_NOALLOC_SCRATCH_BYTES that the library holds
+   on each GPU it runs on until the process ends.  The call allocates and
+   frees nothing.  n is accepted when saq_encode_workspace_bytes(plan, n) <=
+   SAQ_NOALLOC_SCRATCH_BYTES (at D_kept = 864 about 19,000 rows); a larger n
+   gives SAQ_EINVAL with the limit in saq_last_error(), and the caller splits
+   the batch.  Inputs and outputs are as in saq_encode (caller-owned device
+   buffers, asynchronous on `stream`).  Every call on one GPU uses the same
+   array: calls that overlap on one GPU (other streams, other threads,
+   another replay of a captured graph) race and must be ordered by the
+   caller. */
+#define SAQ_NOALLOC_SCRATCH_BYTES (64LL << 20)
+saq_status saq_encode_noalloc(const saq_plan* plan, const float* X_dev, int64_t n,
+                              int32_t rounds, uint8_t* codes_dev, float* factors_dev,
+                              void* stream);
+
 /* Layouts of a projected-row buffer O with leading dimension ld:
    SAQ_LAYOUT_ROWS:  element (vector i, kept dim j) at O[i * ld + j], ld >= D_kept
    SAQ_LAYOUT_DIMS:  element (vector i, kept dim j) at O[j * ld + i], ld >= n,

@@ -60,7 +60,10 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_encode_ref", "saq_estimate_dist_ref", "saq_estimate_multistage_ref",
            "saq_fit_workspace_bytes", "saq_fit_plan_device",
            "saq_encode_batched_workspace_bytes",
-           "saq_encode_batched", "saq_last_error", "saq_version")
+           "saq_encode_batched", "saq_encode_noalloc", "saq_last_error", "saq_version")
+
+# saq_encode_noalloc's fixed device array (SAQ_NOALLOC_SCRATCH_BYTES in saq.h)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 BATCH_MAX = 16
 
@@ -118,6 +121,7 @@ def lib() -> ctypes.CDLL:
         "saq_fit_plan_device": (i32, [P, i64, i32, P, P, i64, P, P]),
         "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
         "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
+        "saq_encode_noalloc": (i32, [P, P, i64, i32, P, P, P]),
         "saq_last_error": (ctypes.c_char_p, []),
         "saq_version": (ctypes.c_char_p, []),
     }
@@ -361,6 +365,19 @@ def encode(plan: Plan, X, rounds: int = 4, codes=None, factors=None, workspace=N
                                 _dev_ptr(ref_ids), rounds, _dev_ptr(codes), _dev_ptr(factors),
                                 _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
                                 _stream_ptr(stream, X.device)))
+    return codes, factors
+
+
+def encode_noalloc(plan: Plan, X, rounds: int = 4, codes=None, factors=None, stream=None):
+    """saq_encode_noalloc: the encode with its workspace in the library's
+    fixed device array (no device allocation in the call; n is limited to
+    what NOALLOC_SCRATCH_BYTES holds for the plan).  Returns (codes, factors);
+    outputs are allocated here only when not given."""
+    _require_cuda_f32(X, "X", plan.D)
+    n = X.shape[0]
+    codes, factors = _alloc_out(plan, n, X.device, codes, factors)
+    _check(lib().saq_encode_noalloc(plan._h, _dev_ptr(X), n, rounds, _dev_ptr(codes),
+                                    _dev_ptr(factors), _stream_ptr(stream, X.device)))
     return codes, factors
 
 

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 
@@ -1427,6 +1428,68 @@ saq_status saq_encode_ref(const saq_plan* p, const float* X, int64_t n, const fl
     if (n > 0 && (!refs || !ref_ids)) return saq::fail(SAQ_EINVAL, "null reference buffer");
     return encode_impl(p, X, n, rounds, codes, factors, ws, ws_bytes, stream,
                        RefRows{refs, ref_ids, K});
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Encode without allocation: the workspace of saq_encode (the tiled
+// projection and the norms) is a file-scope device array instead of a
+// caller buffer.  Each GPU holds its own copy from the library's load until
+// the process ends; its device address is looked up once per device and
+// kept, and only that address is handed to kernels (the array's name is a
+// host-side stand-in in host code).  Nothing in it must start at zero.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SAQ_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device
+saq_status scratch_address(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return saq::fail(SAQ_EUNSUPPORTED, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (ptr == nullptr || (reinterpret_cast<uintptr_t>(ptr) & 255) != 0)
+            return saq::fail(SAQ_EDEVICE, "scratch array has no aligned device address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SAQ_OK;
+}
+}  // namespace
+
+extern "C" {
+
+saq_status saq_encode_noalloc(const saq_plan* p, const float* X, int64_t n, int32_t rounds,
+                              uint8_t* codes, float* factors, void* stream) {
+    if (saq_status st = check_plan(p); st != SAQ_OK) return st;
+    if (n < 0 || rounds < 0) return saq::fail(SAQ_EINVAL, "bad sizes");
+    if (n == 0) return SAQ_OK;
+    const int64_t need = saq_encode_workspace_bytes(p, n);
+    if (need > SAQ_NOALLOC_SCRATCH_BYTES) {
+        int64_t lo = 0, hi = n;      // the largest accepted n for this plan
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) / 2;
+            if (saq_encode_workspace_bytes(p, mid) <= SAQ_NOALLOC_SCRATCH_BYTES) lo = mid; else hi = mid - 1;
+        }
+        return saq::fail(SAQ_EINVAL, "n = " + std::to_string(n) + " exceeds the no-allocation "
+                         "scratch (" + std::to_string(SAQ_NOALLOC_SCRATCH_BYTES >> 20) +
+                         " MiB holds at most " + std::to_string(lo) + " rows for this plan); "
+                         "split the batch or use saq_encode with a workspace");
+    }
+    void* ws = nullptr;
+    if (saq_status st = scratch_address(&ws); st != SAQ_OK) return st;
+    return encode_impl(p, X, n, rounds, codes, factors, ws, SAQ_NOALLOC_SCRATCH_BYTES, stream,
+                       RefRows{nullptr, nullptr, 0});
 }
 
 int64_t saq_encode_batched_workspace_bytes(const saq_batch_item* items, int32_t count,
