@@ -144,57 +144,10 @@ def main():
     t0 = time.time()
     X = ds.rows_torch(a.n, dev)
     fit_rows = X[: min(a.n, 65536)].cpu().numpy()
-    plan = saq.Plan.fit(fit_rows, saq.PlanParams(bits_per_dim=a.bpd, fit_sample=0)).upload(0)
-    torch.cuda.synchronize()
-    setup_s = time.time() - t0
-    n, D, dk = a.n, plan.D, plan.D_kept
-    print(f"# setup {setup_s:.1f}s plan widths={plan.widths} bits={plan.bits} "
-          f"D_kept={dk} code_bytes={plan.code_bytes}", file=sys.stderr, flush=True)
-
     stream = torch.cuda.current_stream(dev)
-    codes = torch.empty((n, plan.code_bytes), dtype=torch.uint8, device=dev)
-    fac = torch.empty((n, plan.n_factors), dtype=torch.float32, device=dev)
-    ws = torch.empty(plan.encode_workspace_bytes(n), dtype=torch.uint8, device=dev)
-    O = torch.empty(((n + 63) // 64, max(dk, 1), 64), dtype=torch.float32, device=dev)
-    nrm = torch.empty(n, dtype=torch.float32, device=dev)
-
-    def step():
-        saq.encode(plan, X, a.rounds, codes, fac, ws, stream)
-
-    ms_step = None
-    if not a.kernels_only:
-        for _ in range(a.warmup):
-            step()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(a.steps):
-            step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_step = e0.elapsed_time(e1) / a.steps
-
-    # per-kernel durations: the same two launches saq_encode makes, bracketed
-    # by events on the launch stream
-    def timed(fn, k):
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
-        for _ in range(2):
-            fn()
-        torch.cuda.synchronize()
-        evs[0].record(stream)
-        for i in range(k):
-            fn()
-            evs[i + 1].record(stream)
-        torch.cuda.synchronize()
-        d = [evs[i].elapsed_time(evs[i + 1]) for i in range(k)]
-        return float(np.mean(d)), float(np.min(d))
-
-    proj_ms, proj_min = timed(lambda: saq.project(plan, X, O, nrm, saq.LAYOUT_TILES, stream),
-                              a.steps)
-    quant_ms, quant_min = timed(lambda: saq.quantize(plan, O, a.rounds, nrm, codes, fac,
-                                                     saq.LAYOUT_TILES, n, stream), a.steps)
-    if ms_step is None:
-        ms_step = proj_ms + quant_ms
+    head = encode_leg(a, X, fit_rows, a.bpd, stream, t0)
+    plan, ms_step = head["plan"], head["ms_step"]
+    n, D, dk = a.n, plan.D, plan.D_kept
     if a.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -204,26 +157,26 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    flops = 2.0 * D * dk * n
-    proj_bytes = n * (4.0 * D + 4.0 * dk + 4.0)        # read X, write O and ||x - c||^2
-    traffic_workload = f"{n:,} x {D}, {a.bpd:g} b/dim, r={a.rounds}"
-    q_valu = recorded_valu("quantize_kernel", traffic_workload)
-    proj_tflops = flops / (proj_ms * 1e-3) / 1e12
-    # the projection forms each FP32 product as six bf16 MFMA products
-    acc64 = bool(plan.info["projection_fp64_totals"])
-    mfma_flops = flops * SPLIT_PRODUCTS
-    mfma_peak = PEAK_BF16_MFMA
-    mfma_tflops = mfma_flops / (proj_ms * 1e-3) / 1e12
-    q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
-    q_gbs = q_bytes / (quant_ms * 1e-3) / 1e9
-    e2e_bytes = n * (4.0 * D + plan.code_bytes + 4.0 * plan.n_factors)
-
     cpu = None
     if not a.no_cpu and not a.kernels_only:
         cpu = cpu_baseline(plan, X, a)
     fit = None if a.kernels_only else fit_leg(a, X, fit_rows, stream)
-    refs = None if a.kernels_only else ref_leg(a, ds, plan, X, codes, fac, ws, stream, ms_step)
-    del X, O, ws, codes, fac
+    refs = None if a.kernels_only else ref_leg(a, ds, plan, X, head["codes"], head["fac"],
+                                                head["ws"], stream, ms_step)
+    for k in ("codes", "fac", "ws"):
+        head.pop(k)
+    other = None
+    if not a.kernels_only:
+        # the second budget of the headline configuration (2 and 4 b/dim)
+        ob = 2.0 if a.bpd != 2.0 else 4.0
+        leg = encode_leg(a, X, fit_rows, ob, stream, time.time())
+        other = {"bits_per_dim": ob, "value": n / (leg["ms_step"] * 1e-3), "unit": "vectors/s",
+                 "ms_per_step": leg["ms_step"],
+                 "segments": {"widths": leg["plan"].widths, "bits": leg["plan"].bits},
+                 "D_kept": leg["plan"].D_kept, "code_bytes": leg["plan"].code_bytes,
+                 **{k: v for k, v in kernel_records(a, leg).items()}}
+        del leg
+    del X
     torch.cuda.empty_cache()
     batched = scans = None
     if a.batched_n > 0 and not a.kernels_only:
@@ -235,6 +188,7 @@ def main():
         serving = serve_leg(a)
         serving_mix = serve_mix_leg(a)
 
+    recs = kernel_records(a, head)
     out = {
         "metric": "SAQ encode vectors/s (D=960, 4 b/dim)" if a.bpd == 4.0 else
                   f"SAQ encode vectors/s (D=960, {a.bpd:g} b/dim)",
@@ -257,42 +211,8 @@ def main():
             "segments": {"widths": plan.widths, "bits": plan.bits},
             "D_kept": dk, "code_bytes": plan.code_bytes,
         },
-        "roofline": {
-            "kernel": ("project_kernel (o = M (x - c), FP32 products as six bf16 MFMA products "
-                       "of exactly split operands, " +
-                       ("FP64 k-tile totals)" if acc64 else "FP32 accumulation)")),
-            "bound": "mfma",
-            "achieved": mfma_tflops,
-            "peak": mfma_peak / 1e12,
-            "unit": "TFLOP/s",
-            "frac": mfma_tflops * 1e12 / mfma_peak,
-            "traffic": recorded_traffic("project_kernel", traffic_workload),
-            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
-            "algorithmic_per_launch": mfma_flops,
-            "fp32_flops_per_launch": flops,
-            "fp32_equivalent_tflops": proj_tflops,
-            "fp32_mfma_peak_tflops": PEAK_FP32_MFMA / 1e12,
-            "algorithmic_bytes_per_launch": proj_bytes,
-            "avg_ms": proj_ms,
-        },
-        "quantize_kernel": {
-            "kernel": "quantize_kernel (grid code, adjustment, factors, packing)",
-            "bound": "alu",
-            "hbm": {"achieved": q_gbs, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                    "frac": q_gbs * 1e9 / PEAK_HBM, "algorithmic_per_launch": q_bytes,
-                    "traffic": recorded_traffic("quantize_kernel", traffic_workload)},
-            "valu": None if q_valu is None else {
-                "achieved": q_valu * 64 / (quant_ms * 1e-3), "peak": VALU_LANE_OPS,
-                "unit": "lane-ops/s", "frac": q_valu * 64 / (quant_ms * 1e-3) / VALU_LANE_OPS,
-                "instructions_per_launch": q_valu},
-            "avg_ms": quant_ms,
-        },
-        "end_to_end": {
-            "bytes_per_vector": e2e_bytes / n,
-            "hbm_frac": e2e_bytes / (ms_step * 1e-3) / PEAK_HBM,
-            "binding_roofline_vectors_per_s": min(PEAK_HBM / (e2e_bytes / n),
-                                                  mfma_peak / (mfma_flops / n)),
-        },
+        **recs,
+        "other_budget": other,
         "cpu_baseline": cpu,
         "fit": fit,
         "reference_vectors": refs,
@@ -301,8 +221,144 @@ def main():
         "serving": serving,
         "serving_mix": serving_mix,
     }
-    out["end_to_end"]["frac_of_binding"] = out["value"] / out["end_to_end"]["binding_roofline_vectors_per_s"]
     print(json.dumps(out), flush=True)
+
+
+def encode_leg(a, X, fit_rows, bpd, stream, t0):
+    """Fit the plan at `bpd` b/dim on the first 65,536 rows, then time the
+    whole encode step (warm-up, then `steps` steps between two events on the
+    launch stream) and each of its two kernels alone (the same launches,
+    each bracketed by events on that stream)."""
+    import torch
+    import paper_2509_12086_amd as saq
+    dev = X.device
+    plan = saq.Plan.fit(fit_rows, saq.PlanParams(bits_per_dim=bpd, fit_sample=0)).upload(0)
+    torch.cuda.synchronize()
+    n, dk = X.shape[0], plan.D_kept
+    print(f"# setup {time.time() - t0:.1f}s {bpd:g} b/dim plan widths={plan.widths} "
+          f"bits={plan.bits} D_kept={dk} code_bytes={plan.code_bytes}", file=sys.stderr,
+          flush=True)
+    codes = torch.empty((n, plan.code_bytes), dtype=torch.uint8, device=dev)
+    fac = torch.empty((n, plan.n_factors), dtype=torch.float32, device=dev)
+    ws = torch.empty(plan.encode_workspace_bytes(n), dtype=torch.uint8, device=dev)
+
+    def step():
+        saq.encode(plan, X, a.rounds, codes, fac, ws, stream)
+
+    ms_step = None
+    if not a.kernels_only:
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(a.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = e0.elapsed_time(e1) / a.steps
+
+    O = torch.empty(((n + 63) // 64, max(dk, 1), 64), dtype=torch.float32, device=dev)
+    nrm = torch.empty(n, dtype=torch.float32, device=dev)
+
+    def timed(fn, k):
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        evs[0].record(stream)
+        for i in range(k):
+            fn()
+            evs[i + 1].record(stream)
+        torch.cuda.synchronize()
+        d = [evs[i].elapsed_time(evs[i + 1]) for i in range(k)]
+        return float(np.mean(d))
+
+    proj_ms = timed(lambda: saq.project(plan, X, O, nrm, saq.LAYOUT_TILES, stream), a.steps)
+    quant_ms = timed(lambda: saq.quantize(plan, O, a.rounds, nrm, codes, fac, saq.LAYOUT_TILES,
+                                          n, stream), a.steps)
+    del O, nrm
+    if ms_step is None:
+        ms_step = proj_ms + quant_ms
+    return {"plan": plan, "bpd": bpd, "n": n, "ms_step": ms_step, "proj_ms": proj_ms,
+            "quant_ms": quant_ms, "codes": codes, "fac": fac, "ws": ws}
+
+
+TRIAL_LANE_OPS = 6   # per Algorithm 1 trial with the division-free accept rule: two
+                     # multiply-adds, two compares, two range compares
+
+
+def kernel_records(a, leg):
+    """Roofline records of one encode leg, every figure on the method's own
+    work: the projection's 2 D D_kept FLOP per vector, the quantize kernel's
+    algorithmic bytes, Algorithm 1's 2 r D_kept trials per vector."""
+    plan, n = leg["plan"], leg["n"]
+    D, dk = plan.D, plan.D_kept
+    proj_ms, quant_ms, ms_step = leg["proj_ms"], leg["quant_ms"], leg["ms_step"]
+    flops = 2.0 * D * dk * n
+    proj_bytes = n * (4.0 * D + 4.0 * dk + 4.0)        # read X, write O and ||x - c||^2
+    workload = f"{n:,} x {D}, {leg['bpd']:g} b/dim, r={a.rounds}"
+    q_valu = recorded_valu("quantize_kernel", workload)
+    achieved = flops / (proj_ms * 1e-3)
+    acc64 = bool(plan.info["projection_fp64_totals"])
+    q_bytes = n * (4.0 * dk + 4.0 + plan.code_bytes + 4.0 * plan.n_factors)
+    q_rate = q_bytes / (quant_ms * 1e-3)
+    e2e_bytes = n * (4.0 * D + plan.code_bytes + 4.0 * plan.n_factors)
+    lane_ops = TRIAL_LANE_OPS * 2.0 * a.rounds * dk       # per vector
+    bind = {"hbm": PEAK_HBM / (e2e_bytes / n),
+            "mfma_bf16": PEAK_BF16_MFMA / (flops / n),
+            "valu": VALU_LANE_OPS / lane_ops}
+    bound = min(bind, key=bind.get)
+    return {
+        "roofline": {
+            "kernel": ("project_kernel (o = M (x - c) on the bf16 matrix cores: FP32 products "
+                       "as six bf16 products of exactly split operands, " +
+                       ("FP64 k-tile totals)" if acc64 else "FP32 accumulation)")),
+            "bound": "mfma",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_BF16_MFMA / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_BF16_MFMA,
+            "traffic": recorded_traffic("project_kernel", workload),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+            "work": "2 D D_kept FLOP per vector (the method's projection)",
+            "algorithmic_per_launch": flops,
+            "algorithmic_bytes_per_launch": proj_bytes,
+            "avg_ms": proj_ms,
+            "frac_of_fp32_mfma_peak": achieved / PEAK_FP32_MFMA,
+            "split_emulation": {
+                "note": "matrix-core work issued by the six bf16 products per FP32 product: "
+                        "MFMA utilisation, not the method's work",
+                "bf16_products_per_fp32_product": SPLIT_PRODUCTS,
+                "issued_tflops": SPLIT_PRODUCTS * achieved / 1e12,
+                "frac_of_bf16_peak": SPLIT_PRODUCTS * achieved / PEAK_BF16_MFMA},
+        },
+        "quantize_kernel": {
+            "kernel": "quantize_kernel (grid code, adjustment, factors, packing)",
+            "bound": "alu",
+            "north_star_target": {"figure": "HBM roofline fraction of the quantize kernel "
+                                            "(algorithmic bytes / time / 8 TB/s)",
+                                  "value": q_rate / PEAK_HBM, "target": 0.6},
+            "hbm": {"achieved": q_rate / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                    "frac": q_rate / PEAK_HBM, "algorithmic_per_launch": q_bytes,
+                    "traffic": recorded_traffic("quantize_kernel", workload)},
+            "valu": None if q_valu is None else {
+                "achieved": q_valu * 64 / (quant_ms * 1e-3), "peak": VALU_LANE_OPS,
+                "unit": "lane-ops/s", "frac": q_valu * 64 / (quant_ms * 1e-3) / VALU_LANE_OPS,
+                "instructions_per_launch": q_valu},
+            "avg_ms": quant_ms,
+        },
+        "end_to_end": {
+            "bytes_per_vector": e2e_bytes / n,
+            "flops_per_vector": flops / n,
+            "trial_lane_ops_per_vector": lane_ops,
+            "hbm_frac": e2e_bytes / (ms_step * 1e-3) / PEAK_HBM,
+            "binding_roofline_vectors_per_s": bind[bound],
+            "binding_unit": bound,
+            "roofline_vectors_per_s": bind,
+            "frac_of_binding": n / (ms_step * 1e-3) / bind[bound],
+        },
+    }
 
 
 def ref_leg(a, ds, plan, X, codes, fac, ws, stream, plain_ms):
@@ -737,23 +793,43 @@ def serve_mix_leg(a):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo", encoding="utf-8"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(plan, X, a):
-    """The FP64 oracle on the host cores, on a bounded sample of the same rows."""
+    """The FP64 oracle on the host cores, on bounded samples of the same rows:
+    every core the process may use (OpenMP over vectors), then one core."""
     import oracle
     cores = len(os.sched_getaffinity(0))
     M, c, _ = plan.arrays()
-    probe = X[:2000].cpu().numpy()
-    t = time.time()
-    oracle.encode(probe, M, c, plan.kept_widths, plan.kept_bits, a.rounds, threads=cores)
-    rate = probe.shape[0] / (time.time() - t)
-    m = int(min(a.n, max(2000, rate * a.cpu_seconds)))
-    rows = X[:m].cpu().numpy()
-    t = time.time()
-    oracle.encode(rows, M, c, plan.kept_widths, plan.kept_bits, a.rounds, threads=cores)
-    dt = time.time() - t
-    return {"value": m / dt, "unit": "vectors/s", "cores": cores, "kind": "oracle",
+
+    def rate_on(threads, seconds):
+        probe = X[:2000].cpu().numpy() if threads > 1 else X[:300].cpu().numpy()
+        t = time.time()
+        oracle.encode(probe, M, c, plan.kept_widths, plan.kept_bits, a.rounds, threads=threads)
+        r = probe.shape[0] / (time.time() - t)
+        m = int(min(a.n, max(probe.shape[0], r * seconds)))
+        rows = X[:m].cpu().numpy()
+        t = time.time()
+        oracle.encode(rows, M, c, plan.kept_widths, plan.kept_bits, a.rounds, threads=threads)
+        dt = time.time() - t
+        return m / dt, m, dt
+
+    v, m, dt = rate_on(cores, a.cpu_seconds)
+    v1, m1, dt1 = rate_on(1, a.cpu_seconds * 0.75)
+    return {"value": v, "unit": "vectors/s", "cores": cores, "kind": "oracle",
             "sample": f"first {m} of the {a.n} rows, full encode (FP64 projection + Algorithm 1), "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s on {cores} threads",
+            "cpu": cpu_model(),
+            "one_core": {"value": v1, "unit": "vectors/s", "cores": 1,
+                         "sample": f"first {m1} rows, {dt1:.1f} s on 1 thread"}}
 
 
 if __name__ == "__main__":

@@ -58,3 +58,29 @@ def test_more_than_one_gpu_exits_with_a_message():
         assert r.returncode == 2
         assert f"--gpus {n} is not supported" in r.stderr
         assert r.stdout == ""
+
+
+def test_roofline_fractions_price_the_methods_own_work():
+    """roofline.frac is the projection's 2 D D_kept FLOP per vector over the
+    measured time and the bf16 matrix-core peak; the six emulation products
+    appear only in their own labelled record; the end-to-end binding
+    roofline takes the method's bytes, FLOPs and trial lane-ops per vector."""
+    from types import SimpleNamespace
+    plan = SimpleNamespace(D=960, D_kept=864, code_bytes=480, n_factors=8,
+                           info={"projection_fp64_totals": 0})
+    a = SimpleNamespace(rounds=4)
+    n = 1_000_000
+    leg = {"plan": plan, "n": n, "bpd": 4.0, "proj_ms": 9.0, "quant_ms": 3.5, "ms_step": 12.8}
+    r = bench.kernel_records(a, leg)
+    flops = 2.0 * 960 * 864 * n
+    assert abs(r["roofline"]["frac"] - flops / 9.0e-3 / 2.5e15) < 1e-12
+    assert r["roofline"]["algorithmic_per_launch"] == flops
+    assert abs(r["roofline"]["split_emulation"]["frac_of_bf16_peak"]
+               - 6 * r["roofline"]["frac"]) < 1e-12
+    q_bytes = n * (4.0 * 864 + 4.0 + 480 + 4.0 * 8)
+    assert abs(r["quantize_kernel"]["hbm"]["frac"] - q_bytes / 3.5e-3 / 8e12) < 1e-12
+    e = r["end_to_end"]
+    assert e["bytes_per_vector"] == 4.0 * 960 + 480 + 32
+    assert e["roofline_vectors_per_s"]["mfma_bf16"] == 2.5e15 / (2.0 * 960 * 864)
+    assert e["binding_roofline_vectors_per_s"] == min(e["roofline_vectors_per_s"].values())
+    assert abs(e["frac_of_binding"] - n / 12.8e-3 / e["binding_roofline_vectors_per_s"]) < 1e-12
