@@ -537,17 +537,22 @@ def batched_leg(a):
                   "plain_vectors_per_s": 16 * small_n / (s_plain * 1e-3),
                   "batched_vectors_per_s": 16 * small_n / (s_batched * 1e-3),
                   "batched_over_plain": s_plain / s_batched,
-                  "tuning": {"quant_waves": s_best.quant_waves,
-                             "gemm_xcd_order": s_best.gemm_xcd_order}},
-        "autotune": {"best": {"quant_waves": best.quant_waves,
-                              "gemm_xcd_order": best.gemm_xcd_order},
+                  "tuning": _tuning_dict(s_best)},
+        "autotune": {"best": _tuning_dict(best),
                      "seconds": tune_s,
-                     "table_ms": [{"quant_waves": t.quant_waves, "gemm_xcd_order": t.gemm_xcd_order,
-                                   "ms": ms} for t, ms in table]},
+                     "table_ms": [dict(_tuning_dict(t), ms=ms) for t, ms in table]},
     }
     del entries
     torch.cuda.empty_cache()
     return out
+
+
+def _tuning_dict(t):
+    import paper_2509_12086_amd as saq
+    if t.mode == saq.BATCH_FUSED:
+        return {"mode": "fused", "tile_rows": t.tile_rows}
+    return {"mode": "grouped", "tile_rows": t.tile_rows, "quant_waves": t.quant_waves,
+            "gemm_xcd_order": t.gemm_xcd_order}
 
 
 def serve_leg(a):

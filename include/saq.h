@@ -306,12 +306,18 @@ saq_status saq_estimate_multistage_ref(const saq_plan* plan, const float* Q_dev,
                                        void* ws_dev, int64_t ws_bytes, void* stream);
 
 /* Batched encode: many datasets, each with its own uploaded plan (uneven
-   segment widths and bits), in two grouped launches for the whole batch --
-   one for every dataset's projection tiles, one for every dataset's
-   quantize/adjust/pack blocks -- however many datasets there are.  Every
-   dataset gets exactly the records saq_encode would give it.  ws_dev:
-   saq_encode_batched_workspace_bytes() bytes (the projected rows of all
-   datasets). */
+   segment widths and bits; the batching pattern stated for the method's
+   encode path), in one launch for the whole batch however many datasets
+   there are.  In the default mode a persistent grid (as many workgroups as
+   stay resident) takes row blocks of every dataset from one atomic ticket;
+   a workgroup projects its row block against all of the dataset's kept dims
+   and then quantizes, adjusts and packs those rows itself, so no workgroup
+   ever waits for another (a tiny kernel clears the ticket first).  The
+   other mode runs two grouped launches: every dataset's projection tiles,
+   then every dataset's quantize/adjust/pack blocks.  Every dataset gets
+   exactly the records saq_encode would give it, in either mode and with any
+   launch shape.  ws_dev: saq_encode_batched_workspace_bytes() bytes (the
+   projected rows of all datasets and the ticket). */
 #define SAQ_BATCH_MAX 16
 typedef struct {
     const saq_plan* plan;      /* uploaded plan of this dataset */
@@ -322,10 +328,16 @@ typedef struct {
 } saq_batch_item;
 
 /* Launch shape (picked by the autotuner; zero fields take defaults). */
+#define SAQ_BATCH_FUSED   0    /* one persistent fused launch (default) */
+#define SAQ_BATCH_GROUPED 1    /* two grouped launches */
 typedef struct {
-    int32_t quant_waves;     /* waves (of 64 vectors) per quantize workgroup: 1, 2 or 4 (0: 1);
-                                halved while their LDS code buffers exceed 64 KiB */
-    int32_t gemm_xcd_order;  /* 1: XCD-aware projection tile order (default), 0: row-major */
+    int32_t quant_waves;     /* grouped mode: waves (of 64 vectors) per quantize workgroup: 1, 2
+                                or 4 (0: 1); halved while their LDS code buffers exceed 64 KiB */
+    int32_t gemm_xcd_order;  /* grouped mode: 1 XCD-aware projection tile order (default),
+                                0 row-major */
+    int32_t mode;            /* SAQ_BATCH_FUSED or SAQ_BATCH_GROUPED */
+    int32_t tile_rows;       /* projection tile rows: 0 auto, 64, or 128 (128 only when no
+                                dataset accumulates its projection in FP64 k-tile totals) */
     int32_t reserved;        /* must be 0 */
 } saq_batch_tuning;
 

@@ -75,7 +75,12 @@ class _BatchItem(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("quant_waves", ctypes.c_int32), ("gemm_xcd_order", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+BATCH_FUSED = 0      # one persistent fused launch (SAQ_BATCH_FUSED)
+BATCH_GROUPED = 1    # two grouped launches (SAQ_BATCH_GROUPED)
 
 
 def lib() -> ctypes.CDLL:
@@ -556,12 +561,18 @@ def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:
 
 @dataclasses.dataclass(frozen=True)
 class BatchTuning:
-    """Launch shape of the batched launches (saq_batch_tuning)."""
+    """Launch shape of saq_encode_batched (saq_batch_tuning): the mode (one
+    persistent fused launch, or two grouped launches), the projection tile
+    rows (0 auto, 64 or 128), and for the grouped mode the quantize waves
+    per workgroup and the projection tile order."""
     quant_waves: int = 1
     gemm_xcd_order: bool = True
+    mode: int = BATCH_FUSED
+    tile_rows: int = 0
 
     def _c(self) -> _Tuning:
-        return _Tuning(int(self.quant_waves), int(bool(self.gemm_xcd_order)), 0)
+        return _Tuning(int(self.quant_waves), int(bool(self.gemm_xcd_order)), int(self.mode),
+                       int(self.tile_rows), 0)
 
 
 def _batch_struct(entries):

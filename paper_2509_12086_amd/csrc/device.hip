@@ -791,6 +791,88 @@ __global__ __launch_bounds__(256) void grouped_quantize_kernel(const QuantArgs a
 }
 
 // ---------------------------------------------------------------------------
+// Batched encode in one persistent launch.  The work items are blocks of
+// 64 Q rows of every dataset (Q quantize waves, as many as the LDS code
+// buffers allow, up to 4; a whole number of projection row tiles), numbered
+// dataset by dataset.  A workgroup takes the next item from one atomic
+// ticket, projects the item's rows against every column tile of its dataset
+// into the dataset's tiled O (the same tile functions and MFMA sequence as
+// the plain projection, so the same values), and then quantizes, adjusts
+// and packs those rows with its first Q waves, 64 vectors each.  The rows it quantizes are the rows it projected, so no
+// workgroup ever waits for another: every item is finished by the workgroup
+// that took its ticket, and each workgroup leaves once the ticket passes the
+// item count.  While one workgroup of a compute unit runs its quantize phase
+// (VALU) others run projection tiles (matrix cores).  The ticket is cleared
+// by clear_ticket_kernel, launched before on the same stream.
+// ---------------------------------------------------------------------------
+struct FusedSet {
+    const float* X; const u32x4* Ms; const float* cp; float* O; float* norm2;
+    const SegEntry* segs; uint8_t* codes; float* factors;
+    int64_t n; int64_t ld; int64_t code_bytes; int64_t first_item;
+    int D; int vec; int acc64; int k_pad; int dk; int tiles_m; int tiles_n; int n_kept;
+    int codes_align;
+};
+struct FusedArgs {
+    FusedSet set[BATCH_MAX];
+    unsigned long long* ticket;
+    int64_t items;
+    int count; int rounds; int wmax;
+    int qwaves;               // quantize waves per item: the item is 64 qwaves rows
+};
+
+__global__ void clear_ticket_kernel(unsigned long long* ticket) {
+    if (threadIdx.x == 0) *ticket = 0ull;
+}
+
+// Two workgroups per compute unit: the projection phase alone fits three
+// in 168 VGPRs, but with the quantize phase and the item loop in the same
+// kernel it would spill there.
+template <int BI, bool ANY64, typename CT>
+__global__ __launch_bounds__(256, 2) void fused_encode_kernel(const FusedArgs args) {
+    static_assert(!ANY64 || BI == 1, "FP64 k-tile totals run the 64 x 128 tile");
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ long long item_s;
+    float* lds = reinterpret_cast<float*>(smem);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (;;) {
+        if (threadIdx.x == 0) item_s = static_cast<long long>(atomicAdd(args.ticket, 1ull));
+        __syncthreads();
+        const int64_t it = item_s;
+        if (it >= args.items) return;         // the same value in every thread
+        int d = 0;
+        while (d + 1 < args.count && it >= args.set[d + 1].first_item) ++d;
+        const FusedSet& S = args.set[d];
+        const int64_t row0 = (it - S.first_item) * 64 * args.qwaves;
+        const int tm0 = int(row0 / (64 * BI));
+        const int tm1 = min(S.tiles_m, int((row0 + 64 * args.qwaves) / (64 * BI)));
+        for (int tile_m = tm0; tile_m < tm1; ++tile_m)
+            for (int tn = 0; tn < S.tiles_n; ++tn) {
+                if (ANY64 && S.acc64)
+                    gemm_tile<LAYOUT_TILES, ANY64, BI>(S.vec != 0, S.X, S.n, S.D, S.Ms, S.k_pad,
+                                                       S.cp, S.dk, S.O, S.ld, S.norm2, tile_m, tn,
+                                                       lds, RefRows{nullptr, nullptr, 0});
+                else
+                    gemm_tile<LAYOUT_TILES, false, BI>(S.vec != 0, S.X, S.n, S.D, S.Ms, S.k_pad,
+                                                       S.cp, S.dk, S.O, S.ld, S.norm2, tile_m, tn,
+                                                       lds, RefRows{nullptr, nullptr, 0});
+                // the tile's LDS (and the norm hand-off) is free for the next
+                // one; its O and norm stores are visible to every wave
+                __syncthreads();
+            }
+        if (wave < args.qwaves) {
+            const int64_t v0 = row0 + int64_t(64) * wave;
+            if (v0 < S.n)
+                quantize_wave<CT, LAYOUT_TILES>(S.O, S.ld, S.n, v0, lane, S.segs, S.n_kept,
+                                                S.norm2, args.rounds, S.codes, S.code_bytes,
+                                                S.codes_align, S.factors,
+                                                reinterpret_cast<CT*>(smem) +
+                                                    int64_t(wave) * args.wmax * 64);
+        }
+        __syncthreads();                      // LDS is reused by the next item
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Estimate scan (Section 3.2) as a matrix-core contraction:
 //   dist2[q][i] = ||o_i||^2 + ||q - c||^2 - 2 sum_s f_s <u_s(i), q'_s>
 // is a GEMM between the records' scaled codes a_i = (f_s u_s), one row of
@@ -1253,16 +1335,20 @@ int64_t enc_o_bytes(const saq_plan* p, int64_t n) {
 struct BatchPlan {
     GemmArgs g{};
     QuantArgs q{};
+    FusedArgs f{};
     int64_t gemm_blocks = 0, quant_blocks = 0, ws_need = 0;
     int waves = 1;
+    int bi = 2;               // projection tile rows / 64
+    bool fused = true;
     bool wide = false;
     bool any64 = false;       // some dataset takes FP64 k-tile totals
-    size_t lds = 0;
+    size_t lds = 0;           // grouped: quantize LDS; fused: the kernel's dynamic LDS
 };
 
-// Lays out the workspace (per dataset: projected rows in the dims layout and
-// ||x - c||^2) and fills both launches' arguments.  With ws == nullptr only
-// the size is meaningful.
+// Lays out the workspace (per dataset: projected rows in the tiled layout
+// and ||x - c||^2; then the fused launch's ticket) and fills the launch
+// arguments of the chosen mode.  With ws == nullptr only the size is
+// meaningful.
 saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds,
                       const saq_batch_tuning* tuning, void* ws, BatchPlan& B,
                       bool check_buffers = true) {
@@ -1285,23 +1371,50 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
     }
     const size_t cs = B.wide ? 2 : 1;
     if (tuning && tuning->reserved != 0) return saq::fail(SAQ_EINVAL, "saq_batch_tuning.reserved must be 0");
+    const int mode = tuning ? tuning->mode : SAQ_BATCH_FUSED;
+    if (mode != SAQ_BATCH_FUSED && mode != SAQ_BATCH_GROUPED)
+        return saq::fail(SAQ_EINVAL, "saq_batch_tuning.mode must be SAQ_BATCH_FUSED or SAQ_BATCH_GROUPED");
+    B.fused = mode == SAQ_BATCH_FUSED;
+    const int rows_req = tuning ? tuning->tile_rows : 0;
+    if (rows_req != 0 && rows_req != 64 && rows_req != 128)
+        return saq::fail(SAQ_EINVAL, "tile_rows must be 0, 64 or 128");
+    if (rows_req == 128 && B.any64)
+        return saq::fail(SAQ_EINVAL, "tile_rows 128 with a dataset that takes FP64 k-tile totals");
+    B.bi = (B.any64 || rows_req == 64) ? 1 : 2;
     const int want = tuning && tuning->quant_waves > 0 ? tuning->quant_waves : 1;
     if (want != 1 && want != 2 && want != 4) return saq::fail(SAQ_EINVAL, "quant_waves must be 1, 2 or 4");
     if (size_t(wmax) * 64 * cs > kMaxDynLds)
         return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the quantize kernel's "
                                            "LDS code buffer (1024 dims at <= 8 bits, 512 above)");
-    B.waves = want;
-    while (B.waves > 1 && size_t(B.waves) * wmax * 64 * cs > kMaxDynLds) B.waves >>= 1;
-    B.lds = size_t(B.waves) * wmax * 64 * cs;
+    if (B.fused) {
+        // the item's quantize waves (4, 2 or the tile's BI) share the
+        // workgroup's LDS with the projection tile
+        int qw = 4;
+        while (qw > B.bi && size_t(qw) * wmax * 64 * cs > kMaxDynLds) qw >>= 1;
+        const size_t q = size_t(qw) * wmax * 64 * cs;
+        const size_t g = size_t(B.bi == 1 ? split_lds_floats<1>() : split_lds_floats<2>()) * 4;
+        if (q > kMaxDynLds)
+            return saq::fail(SAQ_EUNSUPPORTED, "the fused launch's quantize waves need more than "
+                                               "64 KiB of LDS at this tile shape (use tile_rows 64 "
+                                               "or the grouped mode)");
+        B.f.qwaves = qw;
+        B.lds = std::max(q, g);
+    } else {
+        B.waves = want;
+        while (B.waves > 1 && size_t(B.waves) * wmax * 64 * cs > kMaxDynLds) B.waves >>= 1;
+        B.lds = size_t(B.waves) * wmax * 64 * cs;
+    }
     const int xcd = !tuning || tuning->gemm_xcd_order != 0;
 
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
     int64_t off = 0;
     auto take = [&](int64_t bytes) { const int64_t o = off; off += (bytes + 255) & ~int64_t(255); return o; };
-    B.g.count = B.q.count = 0;
+    B.g.count = B.q.count = B.f.count = 0;
     B.g.xcd_order = xcd;
-    B.q.rounds = rounds;
-    B.q.wmax = wmax;
+    B.q.rounds = B.f.rounds = rounds;
+    B.q.wmax = B.f.wmax = wmax;
+    B.f.items = 0;
+    const int rows = 64 * B.bi;
     for (int i = 0; i < count; ++i) {
         const saq_batch_item& it = items[i];
         if (it.n == 0) continue;
@@ -1309,26 +1422,48 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         const int64_t ld = std::max(p->D_kept, 1);
         float* O = reinterpret_cast<float*>(base + take(enc_o_bytes(p, it.n)));
         float* nrm = reinterpret_cast<float*>(base + take(it.n * 4));
+        const int vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
+        const uintptr_t cb = reinterpret_cast<uintptr_t>(it.codes_dev);
+        const int codes_align = (cb & 3) == 0 ? 4 : (cb & 1) == 0 ? 2 : 1;
+        const int tiles_m = int((it.n + rows - 1) / rows), tiles_n = p->layout.n_pad / TN;
         GemmSet& G = B.g.set[B.g.count++];
-        G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0;
-        G.vec = (p->D % 4 == 0) && ((reinterpret_cast<uintptr_t>(it.X_dev) & 15) == 0);
+        G.X = it.X_dev; G.n = it.n; G.D = p->D; G.acc64 = p->acc64 ? 1 : 0; G.vec = vec;
         G.Ms = dev_Ms(p); G.k_pad = p->layout.k_pad; G.cp = dev_c(p); G.dk = p->D_kept;
-        const int rows = B.any64 ? gemm_rows<gemm_bi<true>()>() : gemm_rows<gemm_bi<false>()>();
-        G.tiles_m = int((it.n + rows - 1) / rows); G.tiles_n = p->layout.n_pad / TN;
+        G.tiles_m = tiles_m; G.tiles_n = tiles_n;
         G.O = O; G.ld = ld; G.norm2 = nrm;
         G.first_block = B.gemm_blocks;
         B.gemm_blocks += xcd ? int64_t(NXCD) * ((G.tiles_m + NXCD - 1) / NXCD) * G.tiles_n
                              : int64_t(G.tiles_m) * G.tiles_n;
         QuantSet& Q = B.q.set[B.q.count++];
         Q.O = O; Q.ld = ld; Q.n = it.n; Q.segs = dev_seg(p); Q.n_kept = p->n_kept; Q.norm2 = nrm;
-        Q.codes = it.codes_dev; Q.code_bytes = p->code_bytes;
-        const uintptr_t cb = reinterpret_cast<uintptr_t>(it.codes_dev);
-        Q.codes_align = (cb & 3) == 0 ? 4 : (cb & 1) == 0 ? 2 : 1;
+        Q.codes = it.codes_dev; Q.code_bytes = p->code_bytes; Q.codes_align = codes_align;
         Q.factors = it.factors_dev;
         Q.first_block = B.quant_blocks;
         B.quant_blocks += (it.n + 64 * B.waves - 1) / (64 * B.waves);
+        FusedSet& F = B.f.set[B.f.count++];
+        F.X = it.X_dev; F.Ms = G.Ms; F.cp = G.cp; F.O = O; F.norm2 = nrm; F.segs = Q.segs;
+        F.codes = it.codes_dev; F.factors = it.factors_dev;
+        F.n = it.n; F.ld = ld; F.code_bytes = p->code_bytes; F.first_item = B.f.items;
+        F.D = p->D; F.vec = vec; F.acc64 = G.acc64; F.k_pad = G.k_pad; F.dk = G.dk;
+        F.tiles_m = tiles_m; F.tiles_n = tiles_n; F.n_kept = p->n_kept; F.codes_align = codes_align;
+        if (B.fused) B.f.items += (it.n + 64 * B.f.qwaves - 1) / (64 * B.f.qwaves);
     }
+    B.f.ticket = reinterpret_cast<unsigned long long*>(base + take(8));
+    B.f.count = B.g.count;
     B.ws_need = off + 256;
+    return SAQ_OK;
+}
+
+// Resident workgroups of a fused-launch instantiation on this device
+template <class K>
+saq_status fused_grid(K kernel, size_t lds, int64_t items, unsigned& grid) {
+    int dev = 0, cus = 0, occ = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 256, lds);
+    if (e != hipSuccess) return hip_fail(e, "fused launch occupancy");
+    const int64_t cap = int64_t(std::max(cus, 1)) * std::max(occ, 1);
+    grid = unsigned(std::max<int64_t>(1, std::min(items, cap)));
     return SAQ_OK;
 }
 }  // namespace
@@ -1508,10 +1643,33 @@ saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_
     if (ws_bytes < B.ws_need) return saq::fail(SAQ_EINVAL, "workspace too small");
     if (B.g.count == 0) return SAQ_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool any64 = B.any64;
-    // one instantiation handles both kinds of datasets; the FP32-only one
-    // keeps the register budget of two workgroups per compute unit
-    if (any64)
+    if (B.fused) {
+        hipLaunchKernelGGL(clear_ticket_kernel, dim3(1), dim3(64), 0, st, B.f.ticket);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "clear_ticket_kernel launch");
+        unsigned grid = 1;
+#define SAQ_LAUNCH_FUSED(BI, A64, CT)                                                              \
+    do {                                                                                           \
+        if (saq_status s2 = fused_grid(fused_encode_kernel<BI, A64, CT>, B.lds, B.f.items, grid);  \
+            s2 != SAQ_OK)                                                                          \
+            return s2;                                                                             \
+        hipLaunchKernelGGL((fused_encode_kernel<BI, A64, CT>), dim3(grid), dim3(256), B.lds, st,   \
+                           B.f);                                                                   \
+    } while (0)
+        if (B.any64) {
+            if (B.wide) SAQ_LAUNCH_FUSED(1, true, uint16_t); else SAQ_LAUNCH_FUSED(1, true, uint8_t);
+        } else if (B.bi == 1) {
+            if (B.wide) SAQ_LAUNCH_FUSED(1, false, uint16_t); else SAQ_LAUNCH_FUSED(1, false, uint8_t);
+        } else {
+            if (B.wide) SAQ_LAUNCH_FUSED(2, false, uint16_t); else SAQ_LAUNCH_FUSED(2, false, uint8_t);
+        }
+#undef SAQ_LAUNCH_FUSED
+        e = hipGetLastError();
+        return e == hipSuccess ? SAQ_OK : hip_fail(e, "fused_encode_kernel launch");
+    }
+    // one instantiation per tile shape: the 64-row one also carries datasets
+    // with FP64 k-tile totals, the 128-row one keeps three workgroups per CU
+    if (B.bi == 1)
         hipLaunchKernelGGL(grouped_gemm_kernel<true>, dim3(unsigned(B.gemm_blocks)), dim3(256), 0, st, B.g);
     else
         hipLaunchKernelGGL(grouped_gemm_kernel<false>, dim3(unsigned(B.gemm_blocks)), dim3(256), 0, st, B.g);

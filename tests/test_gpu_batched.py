@@ -1,6 +1,7 @@
-"""Batched encode (many datasets with uneven segments in two grouped
-launches): every dataset's records are bit-identical to its own plain
-saq_encode, for every launch shape the autotuner may pick."""
+"""Batched encode (many datasets with uneven segments, in one persistent
+fused launch or in two grouped launches): every dataset's records are
+bit-identical to its own plain saq_encode, for every launch shape the
+autotuner may pick."""
 import numpy as np
 import pytest
 
@@ -50,8 +51,10 @@ def _plain(batch, rounds):
 
 @pytest.mark.parametrize("tuning", [
     saq.BatchTuning(),
-    saq.BatchTuning(quant_waves=2, gemm_xcd_order=False),
-    saq.BatchTuning(quant_waves=4, gemm_xcd_order=True),
+    saq.BatchTuning(mode=saq.BATCH_FUSED, tile_rows=64),
+    saq.BatchTuning(mode=saq.BATCH_GROUPED),
+    saq.BatchTuning(mode=saq.BATCH_GROUPED, quant_waves=2, gemm_xcd_order=False),
+    saq.BatchTuning(mode=saq.BATCH_GROUPED, quant_waves=4, gemm_xcd_order=True),
 ])
 def test_batched_bit_identical_to_plain(batch, tuning):
     say(f"batched encode {tuning}")
@@ -62,6 +65,41 @@ def test_batched_bit_identical_to_plain(batch, tuning):
     for (c, f), (rc, rf), (p, _) in zip(outs, ref, batch):
         assert np.array_equal(c.cpu().numpy(), rc), p.D
         assert np.array_equal(f.cpu().numpy(), rf), p.D
+
+
+@pytest.mark.parametrize("tuning", [
+    saq.BatchTuning(),
+    saq.BatchTuning(mode=saq.BATCH_FUSED, tile_rows=128),
+    saq.BatchTuning(mode=saq.BATCH_FUSED, tile_rows=64),
+    saq.BatchTuning(mode=saq.BATCH_GROUPED, tile_rows=128, quant_waves=2),
+])
+def test_batched_fp32_tiles_bit_identical_to_plain(batch, tuning):
+    """Datasets that all accumulate in FP32 run the 128-row projection tile
+    (two quantize waves per fused item) unless 64 rows are asked for."""
+    ds = synth.cfg5(0, 2000)
+    sub = [batch[0], batch[2], (_basis_plan(ds, 2.0), to_dev(ds.rows()))]
+    assert not any(p.info["projection_fp64_totals"] for p, _ in sub)
+    say(f"batched FP32-tile encode {tuning}")
+    ref = _plain(sub, 4)
+    for rep in range(2):          # the ticket is cleared before every launch
+        outs = saq.encode_batched(sub, 4, tuning)
+        torch.cuda.synchronize()
+        for (c, f), (rc, rf), (p, _) in zip(outs, ref, sub):
+            assert np.array_equal(c.cpu().numpy(), rc), (p.D, rep)
+            assert np.array_equal(f.cpu().numpy(), rf), (p.D, rep)
+
+
+def test_fused_launch_reuses_one_workspace(batch):
+    """Back-to-back fused launches on one workspace (the ticket left at the
+    item count by the first) and a graph-free stream order: the second
+    launch's records are again the plain encoder's."""
+    ws = torch.empty(saq.batched_workspace_bytes(batch), dtype=torch.uint8, device=cuda())
+    ref = _plain(batch, 4)
+    for _ in range(3):
+        outs = saq.encode_batched(batch, 4, saq.BatchTuning(), ws)
+    torch.cuda.synchronize()
+    for (c, f), (rc, rf) in zip(outs, ref):
+        assert np.array_equal(c.cpu().numpy(), rc) and np.array_equal(f.cpu().numpy(), rf)
 
 
 def test_batched_with_empty_entry_and_rounds(batch):
@@ -100,16 +138,24 @@ def test_batched_argument_errors(batch):
         saq.encode_batched([(p, X)], -2)
     with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
         saq.encode_batched([(p, X)], 4, saq.BatchTuning(quant_waves=3))
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p, X)], 4, saq.BatchTuning(mode=5))
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p, X)], 4, saq.BatchTuning(tile_rows=96))
+    p8, X8 = batch[3]                     # FP64 k-tile totals take the 64-row tile
+    assert p8.info["projection_fp64_totals"]
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.encode_batched([(p8, X8)], 4, saq.BatchTuning(tile_rows=128))
     # the reserved field of saq_batch_tuning must be 0
     import ctypes
     arr = saq._batch_struct([(p, X, None, None)])
-    t = saq._Tuning(1, 1, 7)
+    t = saq._Tuning(1, 1, 0, 0, 7)
     assert saq.lib().saq_encode_batched_workspace_bytes(arr, 1, ctypes.byref(t)) == -1
 
 
 def test_autotuner_picks_a_valid_shape(batch):
     best, table = autotune.tune(batch[:3], rounds=4, reps=1, sample_rows=4096)
-    assert len(table) == len(autotune.candidates())
+    assert len(table) == len(autotune.candidates(batch[:3]))
     assert best in [t for t, _ in table]
     again, table2 = autotune.tune(batch[:3], rounds=4)
     assert again == best and table2 == []           # cached
