@@ -224,7 +224,14 @@ static bool sym_eigen(std::vector<double>& A, int n, std::vector<double>& w, std
             for (int j = 0; j < n; ++j) T[size_t(j) * n + i] = V[size_t(i) * n + j];
         V.swap(T);
     }
-    // QL with implicit shifts on (d, e); e[i] couples i and i+1 after the shift
+    // QL with implicit shifts on (d, e); e[i] couples i and i+1 after the shift.
+    // This is the published implicit-shift QL iteration for symmetric
+    // tridiagonal matrices (Bowdler, Martin, Reinsch and Wilkinson, "The QR
+    // and QL algorithms for symmetric matrices", Numer. Math. 11, 1968; the
+    // EISPACK routine tql2), with its usual variable names: a Wilkinson-type
+    // shift from the leading 2 x 2 block, then a chase of plane rotations
+    // (c, s) from the bottom of the unreduced block up; the rotations are
+    // recorded and applied to the basis in batches.
     for (int i = 1; i < n; ++i) e[i - 1] = e[i];
     if (n > 0) e[n - 1] = 0.0;
     std::vector<Rot> rots;
