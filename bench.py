@@ -104,14 +104,22 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="length of the served-ingestion trace (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the served-ingestion trace (0 = skip the serving legs)")
+    ap.add_argument("--overload-rate", type=float, default=24000.0,
+                    help="request rate of the serving overload point")
+    ap.add_argument("--overload-seconds", type=float, default=4.0,
+                    help="length of the serving overload point (0 = skip)")
+    ap.add_argument("--mix-seconds", type=float, default=5.0,
+                    help="length of the served multi-dataset mix")
     ap.add_argument("--batched-n", type=int, default=1_000_000,
                     help="vectors per dataset in the batched leg (0 = skip)")
     ap.add_argument("--scan-only", action="store_true",
                     help="only the estimate-scan leg (short runs under a profiler)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched leg (short runs under a profiler)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving legs")
     ap.add_argument("--kernels-only", action="store_true",
                     help="only the per-kernel loops (short runs under a profiler)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -139,6 +147,9 @@ def main():
         return
     if a.scan_only:
         print(json.dumps({"estimate_scan": scan_leg(a)}), flush=True)
+        return
+    if a.serve_only:
+        print(json.dumps({"serving": serve_leg(a), "serving_mix": serve_mix_leg(a)}), flush=True)
         return
     ds = synth.cfg2(a.n)
     t0 = time.time()
@@ -559,8 +570,11 @@ def serve_leg(a):
     """Served ingestion: Poisson arrivals at 2,000 requests/s, D=768 rows
     with variance exp(-i/96), sizes lognormal (median 512, sigma 1.5)
     clipped to [1, 65536], budgets uniform over {2, 4, 6} bits/dim (three
-    resident plans).  Rows come from a pinned host pool; latency runs from
-    arrival to the codes and factors being back on the host."""
+    resident plans), for --serve-seconds.  Rows come from a pinned host
+    pool; latency runs from arrival to the codes and factors being back on
+    the host.  Then an overload point: the same stream at --overload-rate
+    requests/s for --overload-seconds, past what the host link and the
+    scheduler sustain, reporting the throughput actually served."""
     import torch
     import synth
     import paper_2509_12086_amd as saq
@@ -571,26 +585,46 @@ def serve_leg(a):
     plans = {b: saq.Plan.from_basis(np.zeros(ds.d), ds.rotation, ds.lam,
                                     saq.PlanParams(bits_per_dim=float(b))).upload(0)
              for b in (2, 4, 6)}
-    t, size, bud = synth.poisson_requests(2000.0, a.serve_seconds, seed=41)
-    trace, off = [], 0
-    for ti, n, b in zip(t, size, bud):
-        n = int(n)
-        if off + n > pool.shape[0]:
-            off = 0
-        trace.append((float(ti), int(b), pool[off:off + n], ENCODE))
-        off += n
+
+    def make_trace(rate, seconds, seed):
+        t, size, bud = synth.poisson_requests(rate, seconds, seed=seed)
+        trace, off = [], 0
+        for ti, n, b in zip(t, size, bud):
+            n = int(n)
+            if off + n > pool.shape[0]:
+                off = 0
+            trace.append((float(ti), int(b), pool[off:off + n], ENCODE))
+            off += n
+        return trace
+
     be = GpuBackend(0, slots=4, rounds=a.rounds)
     for b, p in plans.items():
         be.add_plan(b, p)
-    # warm-up: one request per plan
-    server = Server(be, hbm_budget=32 << 30, max_batch_vectors=262144).start()
+    # warm-up: one request per plan, and one split request
+    server = Server(be, hbm_budget=32 << 30).start()
     for b in plans:
         server.submit(b, pool[:1024]).wait(60)
+    server.submit(4, pool[:40000]).wait(60)
     server.drain()
-    server = Server(be, hbm_budget=32 << 30, max_batch_vectors=262144).start()
-    reqs = replay(server, trace)
-    server.drain(timeout=300)
-    st = server.stats()
+
+    def run(trace, seconds):
+        server = Server(be, hbm_budget=32 << 30, keep_results=False).start()
+        replay(server, trace)
+        server.drain(timeout=600)
+        st = server.stats()
+        offered = sum(x[2].shape[0] for x in trace) / seconds
+        return st, offered
+
+    trace = make_trace(2000.0, a.serve_seconds, 41)
+    st, offered = run(trace, a.serve_seconds)
+    over = None
+    if a.overload_seconds > 0:
+        otrace = make_trace(a.overload_rate, a.overload_seconds, 43)
+        ost, ooff = run(otrace, a.overload_seconds)
+        over = {"rate_req_per_s": a.overload_rate, "seconds": a.overload_seconds,
+                "requests": ost["requests"], "offered_vectors_per_s": ooff,
+                "sustained_vectors_per_s": ost["vectors_per_s"],
+                "p50_ms": ost["p50_ms"], "p99_ms": ost["p99_ms"], "max_queue": ost["max_queue"]}
     # the plain single-launch encoder on the same vectors, already on the device
     per_b = {}
     for _, b, x, _ in trace:
@@ -600,7 +634,6 @@ def serve_leg(a):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    done = 0
     for b, cnt in per_b.items():
         left = cnt
         while left > 0:
@@ -610,15 +643,20 @@ def serve_leg(a):
     e1.record()
     torch.cuda.synchronize()
     plain = total / (e0.elapsed_time(e1) * 1e-3)
+    del Xd, pool
     return {
         "workload": f"Poisson 2000 req/s for {a.serve_seconds:g} s, D=768 exp(-i/96), sizes "
                     "lognormal(median 512, sigma 1.5) clipped to [1, 65536], budgets {2,4,6} b/dim",
+        "server": {"slots": be.slots, "max_batch_vectors": 262144, "split_vectors": 0,
+                   "launch": "grouped", "buffers": "per slot, reused",
+                   "gc": "paused while serving"},
         "requests": st["requests"], "rejected": st["rejected"], "batches": st["batches"],
         "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
         "served_vectors_per_s": st["vectors_per_s"],
-        "offered_vectors_per_s": total / a.serve_seconds,
+        "offered_vectors_per_s": offered,
         "plain_encoder_vectors_per_s": plain,
         "max_queue": st["max_queue"],
+        "overload": over,
     }
 
 
@@ -757,8 +795,8 @@ def serve_mix_leg(a):
         queries[pid] = ds.rows_torch(64, dev, seed_offset=2).cpu().pin_memory()
     torch.cuda.synchronize()
     rng = np.random.default_rng(52)
-    t = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * a.serve_seconds * 1.5) + 10))
-    t = t[t < a.serve_seconds]
+    t = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * a.mix_seconds * 1.5) + 10))
+    t = t[t < a.mix_seconds]
     trace, offs = [], {pid: 0 for pid in pools}
     for ti in t:
         pid = f"d{rng.integers(len(pools))}"
@@ -784,12 +822,12 @@ def serve_mix_leg(a):
     out = {
         "workload": f"8 resident datasets (D {'/'.join(str(d) for d in synth.CFG5_DIMS)}, "
                     f"4 b/dim, 1M stored records each); Poisson {rate:g} req/s for "
-                    f"{a.serve_seconds:g} s, 80 % encodes of log-uniform 1..131072 vectors, "
+                    f"{a.mix_seconds:g} s, 80 % encodes of log-uniform 1..131072 vectors, "
                     "20 % 64-query estimate scans over 1M records; HBM budget 64 GiB",
         "requests": st["requests"], "rejected": st["rejected"], "batches": st["batches"],
         "encode": st["by_kind"][ENCODE], "scan": st["by_kind"][SCAN],
         "encoded_vectors_per_s": st["vectors_per_s"],
-        "scanned_query_record_pairs_per_s": scans * n_store * 64 / a.serve_seconds,
+        "scanned_query_record_pairs_per_s": scans * n_store * 64 / a.mix_seconds,
         "max_inflight_bytes": st["max_inflight_bytes"],
         "max_queue": st["max_queue"],
     }

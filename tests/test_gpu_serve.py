@@ -24,13 +24,16 @@ def setup():
     return ds, X, plans
 
 
-def test_served_encodes_equal_alone(setup):
+@pytest.mark.parametrize("split", [0, 1024])
+def test_served_encodes_equal_alone(setup, split):
+    """With split = 1024 every request above 1,024 vectors runs as chunks on
+    several slots; its joined result must still be its result alone."""
     ds, X, plans = setup
     be = GpuBackend(0, slots=3)
     for pid, p in plans.items():
         be.add_plan(pid, p)
     budget = 512 << 20
-    server = Server(be, hbm_budget=budget, max_batch_vectors=32768).start()
+    server = Server(be, hbm_budget=budget, max_batch_vectors=32768, split_vectors=split).start()
     t, size, bud = synth.poisson_requests(2000.0, 0.05, seed=7, hi=8192)
     trace, off = [], 0
     for ti, n, b in zip(t, size, bud):
