@@ -142,14 +142,28 @@ static void caq_segment(const double *o, int W, int B, int rounds,
     free(x);
 }
 
+/* Sets the OpenMP thread count for the caller's next parallel regions and
+   returns the previous one, which restore_threads() puts back: a call with
+   a thread count must not change it for other code in the process (the
+   OpenMP runtime is shared with every other library loaded there). */
 static int set_threads(int nthreads)
 {
 #ifdef _OPENMP
+    const int prev = omp_get_max_threads();
     if (nthreads > 0) omp_set_num_threads(nthreads);
-    return omp_get_max_threads();
+    return prev;
 #else
     (void)nthreads;
     return 1;
+#endif
+}
+
+static void restore_threads(int prev)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(prev);
+#else
+    (void)prev;
 #endif
 }
 
@@ -175,7 +189,7 @@ int saqo_quantize(const double *O, int64_t n, int32_t Dk,
         sum += seg_w[s];
     }
     if (sum != Dk || n < 0) return 1;
-    set_threads(nthreads);
+    const int prev_threads = set_threads(nthreads);
 #pragma omp parallel
     {
         double *im = (double *)malloc(sizeof(double) * (size_t)(Dk > 0 ? Dk : 1));
@@ -202,6 +216,7 @@ int saqo_quantize(const double *O, int64_t n, int32_t Dk,
         }
         free(im); free(dm);
     }
+    restore_threads(prev_threads);
     return 0;
 }
 
@@ -210,7 +225,7 @@ int saqo_project(const float *X, int64_t n, int32_t D, const float *M, int32_t D
                  const float *c, double *O, double *norm2, int nthreads)
 {
     if (n < 0 || D <= 0 || Dk < 0) return 1;
-    set_threads(nthreads);
+    const int prev_threads = set_threads(nthreads);
 #pragma omp parallel
     {
         double *xc = (double *)malloc(sizeof(double) * (size_t)D);
@@ -231,6 +246,7 @@ int saqo_project(const float *X, int64_t n, int32_t D, const float *M, int32_t D
         }
         free(xc);
     }
+    restore_threads(prev_threads);
     return 0;
 }
 

@@ -256,3 +256,16 @@ def test_pack_roundtrip(oracle_mod):
             pos += pb
         off += w
     assert np.array_equal(out, codes)
+
+
+def test_thread_count_argument_leaves_the_process_setting(oracle_mod):
+    """A call with threads=1 runs on one thread and then restores the OpenMP
+    thread count: the runtime is shared with every library in the process."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    before = gomp.omp_get_max_threads()
+    O = np.random.default_rng(0).standard_normal((50, 16))
+    oracle_mod.quantize(O, [16], [4], rounds=2, threads=1)
+    oracle_mod.project(O.astype(np.float32), np.eye(16, dtype=np.float32),
+                       np.zeros(16, np.float32), threads=1)
+    assert gomp.omp_get_max_threads() == before
