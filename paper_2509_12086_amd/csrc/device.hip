@@ -519,14 +519,25 @@ __device__ __forceinline__ void sweep(const LaneView<LAYOUT>& lv, int col, int W
 }
 
 // Bit planes of one segment, most significant first; dim i -> byte i/8,
-// bit i%8 of the plane.  Built 32 dims at a time into one word per plane and
-// stored as whole 32-bit words when every plane of the segment is 4-byte
-// aligned in memory, else as 16-bit halves, else bytes.
+// bit i%8 of the plane.  The wave's 64 records are packed in its LDS code
+// buffer and then stored record by record, consecutive lanes writing
+// consecutive bytes of a record (coalesced), rather than each lane writing
+// its own record at a stride of code_bytes.
+//
+// Packing, 32 dims at a time: block j's codes are read into registers, its
+// B plane words are formed, and word (block j, plane q from the most
+// significant) of lane L goes to 32-bit slot
+//   (j B + q) 64 + (L ^ ((j B + q) mod 64))
+// of the buffer.  Those slots end at byte (j + 1) B 256 <= (j + 1) 32 64
+// sizeof(CT), the end of block j's codes (B <= 8 sizeof(CT)), so packing
+// overwrites only codes already read (the buffer is rounded up to whole
+// 32-dim blocks for a ragged last block).  The XOR spreads one record's
+// words over the banks for the read-back, and keeps each store of 64 lanes
+// a permutation of one 64-slot row.
 template <typename CT, int B>
-__device__ __forceinline__ void pack_planes(const CT* __restrict__ lc, int W, int lane,
-                                            uint8_t* __restrict__ dst0, int pb, int unit,
-                                            bool live) {
-    for (int j0 = 0; j0 < W; j0 += 32) {
+__device__ __forceinline__ void stage_planes(CT* __restrict__ lc, int W, int lane) {
+    uint32_t* st = reinterpret_cast<uint32_t*>(lc);
+    for (int j0 = 0, j = 0; j0 < W; j0 += 32, ++j) {
         uint32_t word[B];
 #pragma unroll
         for (int p = 0; p < B; ++p) word[p] = 0u;
@@ -544,31 +555,23 @@ __device__ __forceinline__ void pack_planes(const CT* __restrict__ lc, int W, in
                 for (int p = 0; p < B; ++p) word[p] |= ((c >> p) & 1u) << t;
             }
         }
-        if (!live) continue;
-        const int nb = min(4, pb - (j0 >> 3));   // bytes of this word inside the plane
+        // codes and words are different types: keep the compiler from moving
+        // any word store above this block's code loads
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
 #pragma unroll
         for (int p = 0; p < B; ++p) {
-            uint8_t* dst = dst0 + int64_t(B - 1 - p) * pb + (j0 >> 3);
-            const uint32_t w = word[p];
-            if (unit == 4) {
-                *reinterpret_cast<uint32_t*>(dst) = w;
-            } else if (unit == 2) {
-                reinterpret_cast<uint16_t*>(dst)[0] = uint16_t(w);
-                if (nb > 2) reinterpret_cast<uint16_t*>(dst)[1] = uint16_t(w >> 16);
-            } else {
-                for (int k = 0; k < nb; ++k) dst[k] = uint8_t(w >> (8 * k));
-            }
+            const int slot = j * B + (B - 1 - p);
+            st[slot * 64 + (lane ^ (slot & 63))] = word[p];
         }
     }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 template <typename CT>
-__device__ __forceinline__ void pack_segment(const CT* __restrict__ lc, int W, int B, int lane,
-                                             uint8_t* __restrict__ dst0, int pb, int unit,
-                                             bool live) {
+__device__ __forceinline__ void stage_segment(CT* __restrict__ lc, int W, int B, int lane) {
     switch (B) {
 #define SAQ_PACK_CASE(K) \
-    case K: pack_planes<CT, K>(lc, W, lane, dst0, pb, unit, live); break;
+    case K: stage_planes<CT, K>(lc, W, lane); break;
         SAQ_PACK_CASE(1) SAQ_PACK_CASE(2) SAQ_PACK_CASE(3) SAQ_PACK_CASE(4)
         SAQ_PACK_CASE(5) SAQ_PACK_CASE(6) SAQ_PACK_CASE(7) SAQ_PACK_CASE(8)
         default:
@@ -584,6 +587,40 @@ __device__ __forceinline__ void pack_segment(const CT* __restrict__ lc, int W, i
     }
 }
 
+// Stores the staged segment: record r (vector v0 + r, r < 64, v0 + r < n)
+// gets its B pb bytes at codes + (v0 + r) code_bytes + code_off, U bytes per
+// lane and store.  With at most 64 units per record each store covers
+// 64 / units records, consecutive lanes on consecutive units; otherwise it
+// covers 64 consecutive units of one record.
+template <int U>
+__device__ __forceinline__ void store_staged(const uint32_t* __restrict__ st, int B, int pb,
+                                             int lane, uint8_t* __restrict__ codes,
+                                             int64_t code_bytes, int code_off, int64_t v0,
+                                             int64_t n) {
+    const int upr = B * pb / U;                      // units per record
+    const int live = int(min<int64_t>(64, n - v0));  // records of this wave
+    auto unit = [&](int r, int e, int slot, int bo) {
+        const uint32_t w = st[slot * 64 + (r ^ (slot & 63))] >> (8 * bo);
+        uint8_t* dst = codes + (v0 + r) * code_bytes + code_off + e;
+        if (U == 4) *reinterpret_cast<uint32_t*>(dst) = w;
+        else if (U == 2) *reinterpret_cast<uint16_t*>(dst) = uint16_t(w);
+        else *dst = uint8_t(w);
+    };
+    if (upr <= 64) {
+        const int rpi = 64 / upr;                    // records per store
+        const int rr = lane / upr, e = (lane - rr * upr) * U;
+        const int q = e / pb, t = e - q * pb;
+        const int slot = (t >> 2) * B + q, bo = t & 3;
+        if (rr < rpi)
+            for (int r = rr; r < live; r += rpi) unit(r, e, slot, bo);
+    } else {
+        for (int k = lane; k < upr; k += 64) {
+            const int e = k * U, q = e / pb, t = e - q * pb;
+            const int slot = (t >> 2) * B + q, bo = t & 3;
+            for (int r = 0; r < live; ++r) unit(r, e, slot, bo);
+        }
+    }
+}
 // One wave quantizes vectors v0 .. v0+63 (one per lane; v0 % 64 == 0).
 // lc: this wave's code buffer, [max kept width][64] entries of LDS.
 template <typename CT, int LAYOUT>
@@ -604,7 +641,6 @@ __device__ __forceinline__ void quantize_wave(
         lv.p = O + (LAYOUT == LAYOUT_DIMS ? vv : vv * ld);
         lv.sd = LAYOUT == LAYOUT_DIMS ? ld : 1;
     }
-    uint8_t* rec = codes + vv * code_bytes;
     double kept_norm = 0.0;
     float a[QCH], b[QCH];
 
@@ -698,8 +734,16 @@ __device__ __forceinline__ void quantize_wave(
 
         const int pb = (W + 7) >> 3;
         const int al = pb | e.code_off | int(code_bytes) | codes_align;
-        const int unit = (al & 3) == 0 ? 4 : (al & 1) == 0 ? 2 : 1;
-        pack_segment<CT>(lc, W, B, lane, rec + e.code_off, pb, unit, live);
+        stage_segment<CT>(lc, W, B, lane);
+        const uint32_t* st = reinterpret_cast<const uint32_t*>(lc);
+        if ((al & 3) == 0)
+            store_staged<4>(st, B, pb, lane, codes, code_bytes, e.code_off, v0, n);
+        else if ((al & 1) == 0)
+            store_staged<2>(st, B, pb, lane, codes, code_bytes, e.code_off, v0, n);
+        else
+            store_staged<1>(st, B, pb, lane, codes, code_bytes, e.code_off, v0, n);
+        // the next segment's codes overwrite the staged words
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
     if (live) factors[v * (n_kept + 1) + n_kept] = norm2 ? norm2[v] : float(kept_norm);
 }
@@ -1302,7 +1346,8 @@ saq_status launch_quantize(const saq_plan* p, const float* O, int64_t ld, int la
                            const float* norm2, int rounds, uint8_t* codes, float* factors,
                            hipStream_t st) {
     const bool small = p->max_kept_b <= 8;
-    const size_t lds = size_t(std::max(p->max_kept_w, 1)) * 64 * (small ? 1 : 2);
+    // whole 32-dim blocks: a ragged last block's packed words may run past W
+    const size_t lds = size_t(round_up(std::max(p->max_kept_w, 1), 32)) * 64 * (small ? 1 : 2);
     if (lds > kMaxDynLds)
         return saq::fail(SAQ_EUNSUPPORTED, "a kept segment is wider than the quantize kernel's "
                                            "LDS code buffer (1024 dims at <= 8 bits, 512 above)");
@@ -1364,7 +1409,8 @@ saq_status plan_batch(const saq_batch_item* items, int32_t count, int32_t rounds
         if (check_buffers && it.n > 0 && (!it.X_dev || !it.codes_dev || !it.factors_dev))
             return saq::fail(SAQ_EINVAL, "null buffer");
         if (it.n > 0) {
-            wmax = std::max(wmax, it.plan->max_kept_w);
+            // whole 32-dim blocks: a ragged last block's packed words may run past W
+            wmax = std::max(wmax, int(round_up(it.plan->max_kept_w, 32)));
             B.wide |= it.plan->max_kept_b > 8;
             B.any64 |= it.plan->acc64;
         }
