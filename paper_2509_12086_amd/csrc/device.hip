@@ -943,12 +943,124 @@ __global__ __launch_bounds__(256, 2) void fused_encode_kernel(const FusedArgs ar
 // and a pair with LB_s > tau[q] is closed: it gets LB_s and stage s.  Pairs
 // still open after the last segment get the full estimate and stage k.
 // Once no pair of the workgroup is open, the workgroup stops reading codes.
+//
+// Sparse finish: the matrix cores pay for every pair of the tile while most
+// are closed after the first segments (at D = 3072, m = 4 and a 10-nearest
+// threshold, about 3 % of the pairs are open after two segments), so once at
+// most EMS_CAP pairs of the tile are open at a segment start, the tile
+// leaves the MFMA loop.  Its open pairs, with their partial sums, go to a
+// list in LDS; one lane per pair then reads that pair's codes and query
+// values for the next segment, adds f_s (c - h) q' over its dims in FP32,
+// bounds the pair before the segment after it, and either closes it or
+// appends it to the next list.  Every segment thus costs only its still-open
+// pairs, and the waves stay full because the list is rebuilt per segment.
+// The terms and the bound are the MFMA path's; only the summation order
+// inside a segment differs (FP32 either way).
 // ---------------------------------------------------------------------------
 constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
 constexpr int EK = 32;                  // kept dims per k-step
 constexpr int ESTR = EK + 4;            // floats per LDS row (conflict-free b128 reads)
 constexpr int EST_LDS_FLOATS = 2 * EQ * ESTR;          // 18,432 bytes: the query slices
+// open pairs at which a multi-stage tile leaves the matrix cores; two lists
+// of this many (key, partial sum) entries reuse the query-slice LDS
+constexpr int EMS_CAP = 512;
+constexpr int EMS_LANES = 8;    // lanes per open pair in the sparse finish
+static_assert(2 * EMS_CAP * 2 <= EST_LDS_FLOATS, "pair lists must fit the query-slice LDS");
+
+// One open pair's sum over one segment for the multi-stage sparse finish,
+// this lane's share: S = sum of c_j q'_j over the dims of chunks c0, c0 + cs,
+// c0 + 2 cs, ... of 32 dims (the caller turns S into the segment's term
+// f_s (S - h sum_j q'_j), h = (2^B - 1)/2).  rec: the record's bit planes of
+// the segment (plane p at rec + p pb, dim j at byte j/8, bit j%8, most
+// significant plane first); qs: the query's projected values of the
+// segment.  A whole chunk reads 4 bytes per plane unconditionally (they lie
+// inside the plane), a ragged last chunk only the plane's bytes, with zero
+// query values past W.
+template <int B>
+__device__ __forceinline__ float pair_segment(const uint8_t* __restrict__ rec, int W,
+                                              const float* __restrict__ qs, bool qvec,
+                                              const uint64_t* __restrict__ spread, int c0, int cs) {
+    const int pb = (W + 7) >> 3;
+    struct Chunk { uint32_t w[B]; float q[32]; };
+    auto load_full = [&](Chunk& c, int j0) {
+        const uint8_t* src = rec + (j0 >> 3);
+#pragma unroll
+        for (int p = 0; p < B; ++p) __builtin_memcpy(&c.w[p], src + int64_t(p) * pb, 4);
+        if (qvec) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const float4 x = reinterpret_cast<const float4*>(qs + j0)[v];
+                c.q[4 * v] = x.x; c.q[4 * v + 1] = x.y; c.q[4 * v + 2] = x.z; c.q[4 * v + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 32; ++d) c.q[d] = qs[j0 + d];
+        }
+    };
+    auto load_tail = [&](Chunk& c, int j0) {
+        const int b0 = j0 >> 3;
+#pragma unroll
+        for (int p = 0; p < B; ++p) {
+            uint32_t v = 0u;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (b0 + b < pb) v |= uint32_t(rec[int64_t(p) * pb + b0 + b]) << (8 * b);
+            c.w[p] = v;
+        }
+#pragma unroll
+        for (int d = 0; d < 32; ++d) c.q[d] = j0 + d < W ? qs[j0 + d] : 0.f;
+    };
+    // 8 dims per table lookup and plane: the last 8 planes build the low
+    // byte of each code, the planes before them (B > 8) the high byte
+    float acc = 0.f, acc2 = 0.f;
+    auto use = [&](const Chunk& c) {
+#pragma unroll
+        for (int by = 0; by < 4; ++by) {
+            uint64_t lo = 0, hi = 0;
+#pragma unroll
+            for (int p = 0; p < B; ++p) {
+                const uint64_t sp = spread[(c.w[p] >> (8 * by)) & 0xffu];
+                if (p < B - 8) hi = (hi << 1) | sp;
+                else lo = (lo << 1) | sp;
+            }
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                float code = float(uint32_t(lo >> (8 * d)) & 0xffu);
+                if (B > 8) code = fmaf(float(uint32_t(hi >> (8 * d)) & 0xffu), 256.f, code);
+                if (by & 1) acc2 = fmaf(code, c.q[8 * by + d], acc2);
+                else acc = fmaf(code, c.q[8 * by + d], acc);
+            }
+        }
+    };
+    Chunk x;
+    int j0 = 32 * c0;
+    for (; j0 + 32 <= W; j0 += 32 * cs) {
+        load_full(x, j0);
+        use(x);
+    }
+    if (j0 < W) {
+        load_tail(x, j0);
+        use(x);
+    }
+    return acc + acc2;
+}
+
+__device__ __forceinline__ float pair_segment_any(int B, const uint8_t* __restrict__ rec, int W,
+                                                  const float* __restrict__ qs, bool qvec,
+                                                  const uint64_t* __restrict__ spread, int c0,
+                                                  int cs) {
+    switch (B) {
+#define SAQ_PAIR_CASE(K) \
+    case K: return pair_segment<K>(rec, W, qs, qvec, spread, c0, cs);
+        SAQ_PAIR_CASE(1) SAQ_PAIR_CASE(2) SAQ_PAIR_CASE(3) SAQ_PAIR_CASE(4)
+        SAQ_PAIR_CASE(5) SAQ_PAIR_CASE(6) SAQ_PAIR_CASE(7) SAQ_PAIR_CASE(8)
+        SAQ_PAIR_CASE(9) SAQ_PAIR_CASE(10) SAQ_PAIR_CASE(11) SAQ_PAIR_CASE(12)
+        SAQ_PAIR_CASE(13) SAQ_PAIR_CASE(14) SAQ_PAIR_CASE(15) SAQ_PAIR_CASE(16)
+#undef SAQ_PAIR_CASE
+        default: return 0.f;
+    }
+}
 
 // Occupancy: the plain scan fits 4 waves per SIMD without spilling (100
 // VGPRs), the multi-stage variant 3 (its bound state needs about 150).
@@ -959,10 +1071,12 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
-    const float* __restrict__ lbq, const float* __restrict__ tau, uint8_t* __restrict__ stage,
-    float* __restrict__ out) {
+    const float* __restrict__ lbq, const float* __restrict__ qsum, const float* __restrict__ tau,
+    uint8_t* __restrict__ stage, float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
     __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
+    // multi-stage: open-pair counts of alternate bound checks, list fills
+    __shared__ int ms_open[2], ms_fill[2];
     float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds);
     const int t = threadIdx.x;
     {
@@ -970,6 +1084,10 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
 #pragma unroll
         for (int i = 0; i < 8; ++i) v |= uint64_t((t >> i) & 1) << (8 * i);
         spread[t] = v;                    // blockDim.x == 256
+        if (t < 2) {
+            ms_open[t] = 0;
+            ms_fill[t] = 0;
+        }
     }
     __syncthreads();
     const int wave = t >> 6, lane = t & 63, li = lane & 31, lh = lane >> 5;
@@ -1093,47 +1211,94 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // while that pair is live and not pruned (multi-stage mode only)
     auto rec_of = [&](int r) { return r0 + 32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3); };
     uint32_t open = 0;
-    float on2[16];
+    float on2v[16];
     if constexpr (MS) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t i = rec_of(r);
-            on2[r] = i < n ? factors[i * (n_kept + 1) + n_kept] : 0.f;
+            on2v[r] = i < n ? factors[i * (n_kept + 1) + n_kept] : 0.f;
 #pragma unroll
             for (int bj = 0; bj < QB; ++bj)
                 if (i < n && q0 + 32 * bj + li < nq) open |= 1u << (16 * bj + r);
         }
     }
+    auto on2 = [&](int r) { return on2v[r]; };
+    // the lane's records are rbase + roff(r)
+    const int64_t rbase = r0 + 32 * wave + 4 * lh;
+    auto roff = [](int r) { return 8 * (r >> 2) + (r & 3); };
     // close the pairs whose bound before segment si exceeds their threshold;
-    // true while any pair of the workgroup is still open
-    auto prune = [&](int si) -> bool {
+    // returns the number of pairs of the workgroup still open
+    int par = 0;
+    auto prune = [&](int si) -> int {
 #pragma unroll
         for (int bj = 0; bj < QB; ++bj) {
             const int q = q0 + 32 * bj + li;
             if (q >= nq) continue;
             const float lb = lbq[int64_t(q) * n_kept + si], th = tau[q];
+            float* orow = out + int64_t(q) * n + rbase;
+            uint8_t* srow = stage ? stage + int64_t(q) * n + rbase : nullptr;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const uint32_t bit = 1u << (16 * bj + r);
                 if (open & bit) {
-                    const float v = (on2[r] - 2.f * acc[bj][r]) + lb;
+                    const float v = (on2(r) - 2.f * acc[bj][r]) + lb;
                     if (v > th) {
                         open &= ~bit;
-                        const int64_t i = rec_of(r);
-                        out[int64_t(q) * n + i] = v;
-                        if (stage) stage[int64_t(q) * n + i] = uint8_t(si);
+                        orow[roff(r)] = v;
+                        if (srow) srow[roff(r)] = uint8_t(si);
                     }
                 }
             }
         }
-        return __syncthreads_or(open != 0u) != 0;
+        if (open != 0u) atomicAdd(&ms_open[par], __popc(open));
+        __syncthreads();
+        const int c = ms_open[par];
+        // the other counter was last read before an earlier barrier, and
+        // is next added to after a later one
+        if (t == 0) ms_open[par ^ 1] = 0;
+        par ^= 1;
+        return c;
+    };
+    // the open pairs go to list 0 with their partial sums (key: query of the
+    // tile << 8 | record of the tile); call after a bound check, when no
+    // thread reads the query slices any more
+    uint32_t* keys = reinterpret_cast<uint32_t*>(lds);   // [2][EMS_CAP]
+    float* part = lds + 2 * EMS_CAP;                     // [2][EMS_CAP]
+    auto to_list = [&]() {
+        const int k = __popc(open);
+        if (k > 0) {
+            int slot = atomicAdd(&ms_fill[0], k);
+#pragma unroll
+            for (int bj = 0; bj < QB; ++bj)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if (open & (1u << (16 * bj + r))) {
+                        keys[slot] = uint32_t((32 * bj + li) << 8) |
+                                     uint32_t(32 * wave + 8 * (r >> 2) + 4 * lh + (r & 3));
+                        part[slot] = acc[bj][r];
+                        ++slot;
+                    }
+        }
+        open = 0u;
+        __syncthreads();
     };
 
     // the k-steps in order: (segment s, first dim j0)
     int s = 0, j0 = 0;
     while (s < n_kept && segs[s].width <= 0) ++s;
     bool go = s < n_kept;
-    if constexpr (MS) go = go && prune(s);
+    int listed = 0;          // open pairs handed to the sparse finish
+    if constexpr (MS) {
+        if (go) {
+            const int c = prune(s);
+            go = c > 0;
+            if (go && c <= EMS_CAP) {
+                to_list();
+                listed = c;
+                go = false;
+            }
+        }
+    }
     if (go) {
         Raw g;
         fetch(g, s, j0);
@@ -1142,7 +1307,15 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         for (int kt = 0;; ++kt) {
             const int buf = kt & 1;
             if constexpr (MS) {
-                if (kt > 0 && j0 == 0 && !prune(s)) break;
+                if (kt > 0 && j0 == 0) {
+                    const int c = prune(s);
+                    if (c == 0) break;
+                    if (c <= EMS_CAP) {
+                        to_list();
+                        listed = c;
+                        break;
+                    }
+                }
             }
             // the next k-step
             int s1 = s, j1 = j0 + EK;
@@ -1190,7 +1363,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             const int64_t i = rec_of(r);
             if constexpr (MS) {
                 if (open & (1u << (16 * bj + r))) {
-                    orow[i] = on2[r] + qn - 2.f * acc[bj][r];
+                    orow[i] = on2(r) + qn - 2.f * acc[bj][r];
                     if (stage) stage[int64_t(q) * n + i] = uint8_t(n_kept);
                 }
             } else {
@@ -1198,28 +1371,95 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
         }
     }
+
+    if constexpr (MS) {
+        // sparse finish from segment s: list `cur` holds the pairs open at
+        // its start (workgroup-uniform count `listed`)
+        // a pair's chunks of 32 dims are shared by EMS_LANES consecutive lanes
+        const int sub = t & (EMS_LANES - 1), grp = t / EMS_LANES;
+        int cur = 0;
+        for (int si = s; listed > 0 && si < n_kept; ++si) {
+            const SegEntry e = segs[si];
+            const bool qvec = ((dk | e.col) & 3) == 0 && (reinterpret_cast<uintptr_t>(Qp) & 15) == 0;
+            const bool last = si + 1 == n_kept;
+            const float h = 0.5f * float((1 << e.bits) - 1);
+            // a pair with partial sum acc after segment si: the full estimate
+            // after the last segment, else closed by the bound before si + 1
+            // or appended to the next list
+            auto ms_close = [&](float o2, float acc, int q, int64_t oi, uint32_t key) {
+                if (last) {
+                    out[oi] = o2 + qn2[q] - 2.f * acc;
+                    if (stage) stage[oi] = uint8_t(n_kept);
+                    return;
+                }
+                const float v = (o2 - 2.f * acc) + lbq[int64_t(q) * n_kept + si + 1];
+                if (v > tau[q]) {
+                    out[oi] = v;
+                    if (stage) stage[oi] = uint8_t(si + 1);
+                } else {
+                    const int slot = atomicAdd(&ms_fill[cur ^ 1], 1);
+                    keys[(cur ^ 1) * EMS_CAP + slot] = key;
+                    part[(cur ^ 1) * EMS_CAP + slot] = acc;
+                }
+            };
+            constexpr int G = 256 / EMS_LANES;     // lane groups
+            for (int k = grp; k < listed; k += G) {
+                const uint32_t key = keys[cur * EMS_CAP + k];
+                const int q = q0 + int(key >> 8);
+                const int64_t i = r0 + int(key & 255u);
+                float S = pair_segment_any(e.bits, codes + i * code_bytes + e.code_off, e.width,
+                                           Qp + int64_t(q) * dk + e.col, qvec, spread, sub,
+                                           EMS_LANES);
+                // the group's lanes are consecutive: a butterfly leaves the
+                // pair's sum in all of them
+#pragma unroll
+                for (int o = 1; o < EMS_LANES; o <<= 1) S += __shfl_xor(S, o);
+                if (sub != 0) continue;
+                const float* fi = factors + i * (n_kept + 1);
+                const float acc = part[cur * EMS_CAP + k] +
+                                  fi[si] * (S - h * qsum[int64_t(q) * n_kept + si]);
+                ms_close(fi[n_kept], acc, q, int64_t(q) * n + i, key);
+            }
+            __syncthreads();
+            listed = ms_fill[cur ^ 1];
+            // list `cur` is spent: its fill is cleared before anyone appends
+            // to it again, two segments on
+            if (t == 0) ms_fill[cur] = 0;
+            __syncthreads();
+            cur ^= 1;
+        }
+    }
 }
 
 // sigma_s of Section 4.3 for query blockIdx.y and kept segment blockIdx.x:
 // ||S_s q'_s||, the standard deviation over the data of <o_s, q_s>.  A wave
 // takes rows of the segment's block (coalesced along the row), the query
-// slice sits in LDS.
+// slice sits in LDS.  Also qsum: the plain sum of the slice, which turns the
+// multi-stage sparse finish's sum of c_j q'_j into the segment's term.
 constexpr int SIG_MAXW = 4096;
 __global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp, int dk,
                                                     const SegEntry* __restrict__ segs, int n_kept,
                                                     const float* __restrict__ S,
-                                                    float* __restrict__ sig) {
+                                                    float* __restrict__ sig,
+                                                    float* __restrict__ qsum) {
     __shared__ float qs[SIG_MAXW];
-    __shared__ float part[4];
+    __shared__ float part[4], psum[4];
     const int si = blockIdx.x, q = blockIdx.y;
     int64_t off = 0;
     for (int t = 0; t < si; ++t) off += int64_t(segs[t].width) * segs[t].width;
     const SegEntry e = segs[si];
     const int W = e.width;
     const float* qrow = Qp + int64_t(q) * dk + e.col;
-    for (int j = threadIdx.x; j < W; j += 256) qs[j] = qrow[j];
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float qt = 0.f;
+    for (int j = threadIdx.x; j < W; j += 256) {
+        qs[j] = qrow[j];
+        qt += qrow[j];
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) qt += __shfl_xor(qt, d);
+    if (lane == 0) psum[wave] = qt;
+    __syncthreads();
     float v = 0.f;
     for (int i = wave; i < W; i += 4) {
         const float* row = S + off + int64_t(i) * W;
@@ -1231,7 +1471,10 @@ __global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp
     }
     if (lane == 0) part[wave] = v;
     __syncthreads();
-    if (threadIdx.x == 0) sig[int64_t(q) * n_kept + si] = sqrtf((part[0] + part[1]) + (part[2] + part[3]));
+    if (threadIdx.x == 0) {
+        sig[int64_t(q) * n_kept + si] = sqrtf((part[0] + part[1]) + (part[2] + part[3]));
+        qsum[int64_t(q) * n_kept + si] = (psum[0] + psum[1]) + (psum[2] + psum[3]);
+    }
 }
 
 // lbq[q][s] = ||q - c||^2 - 2 m sum_{t >= s} sigma_t, one thread per query
@@ -1733,8 +1976,9 @@ saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_
 int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     if (!p || nq < 0) return -1;
     const int64_t q = std::max(nq, 1);
-    // Qp [nq x D_kept], ||q - c||^2 [nq], sigma and stage bounds [nq x n_kept] each
-    return q * std::max(p->D_kept, 1) * 4 + q * 4 + 2 * q * std::max(p->n_kept, 1) * 4 + 512;
+    // Qp [nq x D_kept], ||q - c||^2 [nq]; sigma, stage bounds and segment
+    // sums of q' [nq x n_kept] each
+    return q * std::max(p->D_kept, 1) * 4 + q * 4 + 3 * q * std::max(p->n_kept, 1) * 4 + 512;
 }
 
 }  // extern "C"
@@ -1760,11 +2004,11 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
     if (nq <= 32)
         hipLaunchKernelGGL((estimate_kernel<false, 1>), grid, dim3(256), 0, st, Qp, nq,
                            std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
-                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, out);
+                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out);
     else
         hipLaunchKernelGGL((estimate_kernel<false, 2>), grid, dim3(256), 0, st, Qp, nq,
                            std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
-                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, out);
+                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
@@ -1796,10 +2040,11 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     float* qn2 = Qp + int64_t(nq) * dk;
     float* sig = qn2 + nq;
     float* lbq = sig + int64_t(nq) * p->n_kept;
+    float* qsum = lbq + int64_t(nq) * p->n_kept;
     saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st, RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
     hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq)), dim3(256), 0, st, Qp, dk,
-                       dev_seg(p), p->n_kept, dev_S(p), sig);
+                       dev_seg(p), p->n_kept, dev_S(p), sig, qsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "sigma_kernel launch");
     hipLaunchKernelGGL(stage_bound_kernel, dim3(unsigned((nq + 255) / 256)), dim3(256), 0, st, sig, qn2,
@@ -1809,11 +2054,11 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
     if (nq <= 32)
         hipLaunchKernelGGL((estimate_kernel<true, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
                            stage, out);
     else
         hipLaunchKernelGGL((estimate_kernel<true, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, tau,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
                            stage, out);
     e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");

@@ -103,13 +103,23 @@ def test_multistage_matches_oracle(gauss):
 
 
 def test_multistage_no_threshold_is_the_plain_scan(gauss):
+    """With tau = +inf nothing closes.  Tiles with many open pairs run the
+    plain scan's MFMA sequence and give its values bit for bit; tiles with
+    few pairs (the last query tile here: 2 queries x 128 records) take the
+    one-lane-per-pair finish from the first segment, whose sums differ
+    from the plain scan's only in order, within its FP32 tolerance."""
     S = gauss
     Q = S["ds"].queries(66)
     d2, st = _device_ms(S, Q, 4.0, np.full(66, np.inf))
     assert np.all(st == len(S["plan"].kept_widths))
     plain = saq.estimate_dist(S["plan"], to_dev(Q), to_dev(S["packed"]), to_dev(S["fac"]))
     torch.cuda.synchronize()
-    assert np.array_equal(d2, plain.cpu().numpy())
+    plain = plain.cpu().numpy()
+    # full 64-query x 128-record tiles: all 8,192 pairs open, MFMA to the end
+    full = (S["packed"].shape[0] // 128) * 128
+    assert np.array_equal(d2[:64, :full], plain[:64, :full])
+    scale = _scale(S, Q)
+    assert np.max(np.abs(d2 - plain) / scale) < TOL
     _check(S, Q, 4.0, np.full(66, np.inf), "tau=+inf")
 
 
