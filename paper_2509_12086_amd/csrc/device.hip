@@ -1352,22 +1352,42 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
 
     // lane: query q0 + 32 bj + li; for register r the record
     // r0 + 32 wave + 8 (r/4) + 4 lh + r%4
+    const bool vec_out = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
 #pragma unroll
     for (int bj = 0; bj < QB; ++bj) {
         const int q = q0 + 32 * bj + li;
         if (q >= nq) continue;
         const float qn = qn2[q];
         float* orow = out + int64_t(q) * n;
+        if constexpr (MS) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t i = rec_of(r);
-            if constexpr (MS) {
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = rec_of(r);
                 if (open & (1u << (16 * bj + r))) {
                     orow[i] = on2(r) + qn - 2.f * acc[bj][r];
                     if (stage) stage[int64_t(q) * n + i] = uint8_t(n_kept);
                 }
-            } else {
-                if (i < n) orow[i] = factors[i * (n_kept + 1) + n_kept] + qn - 2.f * acc[bj][r];
+            }
+        } else {
+            // records 4g .. 4g + 3 of the lane are consecutive: one 16-byte
+            // store when all four exist and the row is 16-byte aligned (one
+            // store instruction then writes 32 B runs of 32 rows, not 4 B)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int64_t i0 = rec_of(4 * g);
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = i0 + e < n ? factors[(i0 + e) * (n_kept + 1) + n_kept] + qn -
+                                            2.f * acc[bj][4 * g + e]
+                                      : 0.f;
+                if (i0 + 3 < n && vec_out) {
+                    *reinterpret_cast<float4*>(orow + i0) = make_float4(v[0], v[1], v[2], v[3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (i0 + e < n) orow[i0 + e] = v[e];
+                }
             }
         }
     }
@@ -1432,19 +1452,24 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
 }
 
 // sigma_s of Section 4.3 for query blockIdx.y and kept segment blockIdx.x:
-// ||S_s q'_s||, the standard deviation over the data of <o_s, q_s>.  A wave
-// takes rows of the segment's block (coalesced along the row), the query
-// slice sits in LDS.  Also qsum: the plain sum of the slice, which turns the
-// multi-stage sparse finish's sum of c_j q'_j into the segment's term.
+// ||S_s q'_s||, the standard deviation over the data of <o_s, q_s>.  The
+// segment's rows are split into SIG_RB contiguous blocks (blockIdx.z), so a
+// single query still fills the chip; each workgroup writes the sum of
+// squares of its rows, and stage_bound_kernel adds the blocks in a fixed
+// order.  A wave takes rows of the block (coalesced along the row), the
+// query slice sits in LDS.  Block 0 also writes qsum: the plain sum of the
+// slice, which turns the multi-stage sparse finish's sum of c_j q'_j into
+// the segment's term.
 constexpr int SIG_MAXW = 4096;
+constexpr int SIG_RB = 8;
 __global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp, int dk,
                                                     const SegEntry* __restrict__ segs, int n_kept,
                                                     const float* __restrict__ S,
-                                                    float* __restrict__ sig,
+                                                    float* __restrict__ sig_part,
                                                     float* __restrict__ qsum) {
     __shared__ float qs[SIG_MAXW];
     __shared__ float part[4], psum[4];
-    const int si = blockIdx.x, q = blockIdx.y;
+    const int si = blockIdx.x, q = blockIdx.y, rb = blockIdx.z;
     int64_t off = 0;
     for (int t = 0; t < si; ++t) off += int64_t(segs[t].width) * segs[t].width;
     const SegEntry e = segs[si];
@@ -1461,7 +1486,8 @@ __global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp
     if (lane == 0) psum[wave] = qt;
     __syncthreads();
     float v = 0.f;
-    for (int i = wave; i < W; i += 4) {
+    const int i0 = int(int64_t(W) * rb / SIG_RB), i1 = int(int64_t(W) * (rb + 1) / SIG_RB);
+    for (int i = i0 + wave; i < i1; i += 4) {
         const float* row = S + off + int64_t(i) * W;
         float y = 0.f;
         for (int j = lane; j < W; j += 64) y = fmaf(row[j], qs[j], y);
@@ -1472,21 +1498,24 @@ __global__ __launch_bounds__(256) void sigma_kernel(const float* __restrict__ Qp
     if (lane == 0) part[wave] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        sig[int64_t(q) * n_kept + si] = sqrtf((part[0] + part[1]) + (part[2] + part[3]));
-        qsum[int64_t(q) * n_kept + si] = (psum[0] + psum[1]) + (psum[2] + psum[3]);
+        sig_part[(int64_t(q) * n_kept + si) * SIG_RB + rb] = (part[0] + part[1]) + (part[2] + part[3]);
+        if (rb == 0) qsum[int64_t(q) * n_kept + si] = (psum[0] + psum[1]) + (psum[2] + psum[3]);
     }
 }
 
-// lbq[q][s] = ||q - c||^2 - 2 m sum_{t >= s} sigma_t, one thread per query
-__global__ __launch_bounds__(256) void stage_bound_kernel(const float* __restrict__ sig,
+// lbq[q][s] = ||q - c||^2 - 2 m sum_{t >= s} sigma_t, one thread per query;
+// sigma_t from sigma_kernel's row-block sums of squares, added in a fixed order
+__global__ __launch_bounds__(256) void stage_bound_kernel(const float* __restrict__ sig_part,
                                                           const float* __restrict__ qn2, int nq,
                                                           int n_kept, float m,
                                                           float* __restrict__ lbq) {
+    static_assert(SIG_RB == 8, "the fixed summation order below");
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     float t = 0.f;
     for (int si = n_kept - 1; si >= 0; --si) {
-        t += sig[int64_t(q) * n_kept + si];
+        const float* p = sig_part + (int64_t(q) * n_kept + si) * SIG_RB;
+        t += sqrtf(((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7])));
         lbq[int64_t(q) * n_kept + si] = qn2[q] - 2.f * m * t;
     }
 }
@@ -1976,9 +2005,10 @@ saq_status saq_encode_batched(const saq_batch_item* items, int32_t count, int32_
 int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     if (!p || nq < 0) return -1;
     const int64_t q = std::max(nq, 1);
-    // Qp [nq x D_kept], ||q - c||^2 [nq]; sigma, stage bounds and segment
-    // sums of q' [nq x n_kept] each
-    return q * std::max(p->D_kept, 1) * 4 + q * 4 + 3 * q * std::max(p->n_kept, 1) * 4 + 512;
+    // Qp [nq x D_kept], ||q - c||^2 [nq], the row-block sums of squares
+    // behind sigma [nq x n_kept x 8], stage bounds and segment sums of q'
+    // [nq x n_kept] each
+    return q * std::max(p->D_kept, 1) * 4 + q * 4 + (8 + 2) * q * std::max(p->n_kept, 1) * 4 + 512;
 }
 
 }  // extern "C"
@@ -2038,12 +2068,12 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     const int dk = std::max(p->D_kept, 1);
     float* Qp = reinterpret_cast<float*>(base);
     float* qn2 = Qp + int64_t(nq) * dk;
-    float* sig = qn2 + nq;
-    float* lbq = sig + int64_t(nq) * p->n_kept;
+    float* sig = qn2 + nq;                                 // [nq][n_kept][SIG_RB]
+    float* lbq = sig + int64_t(nq) * p->n_kept * SIG_RB;
     float* qsum = lbq + int64_t(nq) * p->n_kept;
     saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st, RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
-    hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq)), dim3(256), 0, st, Qp, dk,
+    hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq), SIG_RB), dim3(256), 0, st, Qp, dk,
                        dev_seg(p), p->n_kept, dev_S(p), sig, qsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "sigma_kernel launch");
