@@ -1226,6 +1226,9 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // the lane's records are rbase + roff(r)
     const int64_t rbase = r0 + 32 * wave + 4 * lh;
     auto roff = [](int r) { return 8 * (r >> 2) + (r & 3); };
+    // rows of out (and stage) start 16-byte (4-byte) aligned
+    const bool vec_ms = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0 &&
+                        (reinterpret_cast<uintptr_t>(stage) & 3) == 0;
     // close the pairs whose bound before segment si exceeds their threshold;
     // returns the number of pairs of the workgroup still open
     int par = 0;
@@ -1237,16 +1240,33 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             const float lb = lbq[int64_t(q) * n_kept + si], th = tau[q];
             float* orow = out + int64_t(q) * n + rbase;
             uint8_t* srow = stage ? stage + int64_t(q) * n + rbase : nullptr;
+            // records 4g .. 4g + 3 are consecutive: when all four close
+            // here, one 16-byte value store and one 4-byte stage store
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const uint32_t bit = 1u << (16 * bj + r);
-                if (open & bit) {
-                    const float v = (on2(r) - 2.f * acc[bj][r]) + lb;
-                    if (v > th) {
-                        open &= ~bit;
-                        orow[roff(r)] = v;
-                        if (srow) srow[roff(r)] = uint8_t(si);
-                    }
+            for (int g = 0; g < 4; ++g) {
+                const uint32_t gbits = 0xfu << (16 * bj + 4 * g);
+                if ((open & gbits) == 0u) continue;
+                float v[4];
+                uint32_t close = 0u;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 4 * g + e;
+                    v[e] = (on2(r) - 2.f * acc[bj][r]) + lb;
+                    if ((open & (1u << (16 * bj + r))) && v[e] > th) close |= 1u << (16 * bj + r);
+                }
+                if (close == 0u) continue;
+                open &= ~close;
+                const int o = roff(4 * g);
+                if (close == gbits && vec_ms) {
+                    *reinterpret_cast<float4*>(orow + o) = make_float4(v[0], v[1], v[2], v[3]);
+                    if (srow) *reinterpret_cast<uint32_t*>(srow + o) = uint32_t(si) * 0x01010101u;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (close & (1u << (16 * bj + 4 * g + e))) {
+                            orow[o + e] = v[e];
+                            if (srow) srow[o + e] = uint8_t(si);
+                        }
                 }
             }
         }
