@@ -155,6 +155,34 @@ def test_multistage_wide_bits_from_parts():
     _check(S, Q, 3.0, tau, "wide bits")
 
 
+def test_multistage_ragged_widths():
+    """Segment widths that are not multiples of 8 or 32 (odd plane byte
+    counts, so unaligned plane offsets and ragged last chunks on both the
+    matrix-core and the one-group-per-pair paths), 1- to 12-bit codes, a
+    ragged record count, and query counts that put a tile on either path
+    from the first segment (1, 3 and 70 queries)."""
+    rng = np.random.default_rng(23)
+    widths, bits = [13, 37, 70, 9, 51, 3, 20], [12, 9, 5, 7, 3, 1, 0]
+    D = sum(widths)
+    kept = sum(w for w, b in zip(widths, bits) if b > 0)
+    sd = np.concatenate([np.full(w, v) for w, v in zip(widths, (3.0, 2.0, 1.2, 0.9, 0.6, 0.4, 0.2))])
+    Mw = np.eye(D, dtype=np.float32)[:kept]
+    plan = saq.Plan.from_parts(widths, bits, Mw, np.zeros(D, np.float32), variances=sd ** 2).upload(0)
+    assert plan.code_bytes % 4 != 0
+    X = (rng.standard_normal((1337, D)) * sd).astype(np.float32)
+    packed, fac, codes = oracle_records(plan, X, 4)
+    S = dict(plan=plan, P=np.eye(D)[:kept], lam=(sd ** 2)[:kept], packed=packed, fac=fac,
+             codes=codes)
+    M, c, _ = plan.arrays()
+    for nq, m in ((1, 4.0), (3, 2.0), (70, 4.0)):
+        Q = (rng.standard_normal((nq, D)) * sd).astype(np.float32)
+        plain = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
+                                fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
+        tau = np.sort(plain, axis=1)[:, 9]
+        st, _ = _check(S, Q, m, tau, f"ragged widths nq={nq}")
+        assert (st < len(plan.kept_widths)).mean() > 0.3
+
+
 def test_multistage_argument_errors(gauss):
     S = gauss
     plan = S["plan"]
