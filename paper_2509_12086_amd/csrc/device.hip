@@ -960,8 +960,11 @@ __global__ __launch_bounds__(256, 2) void fused_encode_kernel(const FusedArgs ar
 constexpr int ER = 128;                 // records per estimate tile
 constexpr int EQ = 64;                  // queries per estimate tile
 constexpr int EK = 32;                  // kept dims per k-step
-constexpr int ESTR = EK + 4;            // floats per LDS row (conflict-free b128 reads)
-constexpr int EST_LDS_FLOATS = 2 * EQ * ESTR;          // 18,432 bytes: the query slices
+// the query slices in LDS: per buffer, bf16 terms 0..2 of each query's 32
+// dims, rows of EROW bf16 (80 bytes: 16 lanes' 16-byte reads of 16
+// consecutive rows hit distinct banks)
+constexpr int EROW = EK + 8;
+constexpr int EST_LDS_FLOATS = 2 * 3 * EQ * EROW / 2;  // 30,720 bytes
 // open pairs at which a multi-stage tile leaves the matrix cores; two lists
 // of this many (key, partial sum) entries reuse the query-slice LDS
 constexpr int EMS_CAP = 512;
@@ -1072,12 +1075,17 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
     const float* __restrict__ lbq, const float* __restrict__ qsum, const float* __restrict__ tau,
-    uint8_t* __restrict__ stage, float* __restrict__ out) {
+    uint8_t* __restrict__ stage, float* __restrict__ out, const u32x4* __restrict__ Qs, int qg) {
     __shared__ __attribute__((aligned(16))) float lds[EST_LDS_FLOATS];
     __shared__ uint64_t spread[256];      // bit i of the index -> bit 8 i
     // multi-stage: open-pair counts of alternate bound checks, list fills
     __shared__ int ms_open[2], ms_fill[2];
-    float (*Bs)[EQ * ESTR] = reinterpret_cast<float (*)[EQ * ESTR]>(lds);
+    // query slice term tm of buffer b, query row q, dims d..d+7: 16 bytes at
+    // bq(b, tm, q, d)
+    auto bq = [&](int b, int tm, int q, int d) {
+        return reinterpret_cast<u32x4*>(reinterpret_cast<__bf16*>(lds) +
+                                        ((b * 3 + tm) * EQ + q) * EROW + d);
+    };
     const int t = threadIdx.x;
     {
         uint64_t v = 0;
@@ -1108,8 +1116,12 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const bool qlive = q0 + qq < nq;
     const float* qrow = Qp + int64_t(qlive ? q0 + qq : 0) * dk;
 
-    struct Raw { uint32_t w[16]; float q[8]; float fs; };
-    float Areg[16];     // this lane's A operand of the current k-step
+    // the k-step's raw inputs: plane words, the staged query dims as three
+    // bf16 terms, the segment factor
+    struct Raw { uint32_t w[16]; u32x4 q[3]; float fs; };
+    // this lane's A operand of the current k-step: f_s (c - h) of its 16 dims
+    // as three exact bf16 terms, for each half (dims 16 lh + 8 m .. + 7)
+    u32x4 Areg[3][2];
     // bits of a segment the scan reads: all of them, or the first `prefix`
     // (progressive approximation, Section 3.2)
     auto used_bits = [&](int B) { return (prefix > 0 && prefix < B) ? prefix : B; };
@@ -1136,18 +1148,25 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
             g.w[p] = w;
         }
-        if (qlive && j0 + EK <= W && ((dk | e.col) & 3) == 0) {
-            // whole k-step, 16-byte aligned: two vector loads
-            const float4* q4 = reinterpret_cast<const float4*>(qrow + e.col + j0 + qd);
-            const float4 a4 = q4[0], b4 = q4[1];
-            g.q[0] = a4.x; g.q[1] = a4.y; g.q[2] = a4.z; g.q[3] = a4.w;
-            g.q[4] = b4.x; g.q[5] = b4.y; g.q[6] = b4.z; g.q[7] = b4.w;
+        if ((e.col & 7) == 0) {
+            // the scan's pre-split query (8-dim groups; dims past the
+            // segment meet zero codes, groups past D_kept are zero)
+            const u32x4* src = Qs + (int64_t(qlive ? q0 + qq : 0) * qg + ((e.col + j0 + qd) >> 3)) * 3;
+#pragma unroll
+            for (int tm = 0; tm < 3; ++tm) g.q[tm] = qlive ? src[tm] : u32x4{0u, 0u, 0u, 0u};
         } else {
+            float qv[8];
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 const int j = j0 + qd + d;
-                g.q[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
+                qv[d] = (qlive && j < W) ? qrow[e.col + j] : 0.f;
             }
+            uint32_t t0[4], t1[4], t2[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) split3(qv[2 * k], qv[2 * k + 1], t0[k], t1[k], t2[k]);
+            g.q[0] = u32x4{t0[0], t0[1], t0[2], t0[3]};
+            g.q[1] = u32x4{t1[0], t1[1], t1[2], t1[3]};
+            g.q[2] = u32x4{t2[0], t2[1], t2[2], t2[3]};
         }
         // the b-bit prefix estimates with the stored factor times 2^(B - b);
         // the factor changes only where a segment starts
@@ -1194,10 +1213,16 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
 #pragma unroll
         for (int d = 0; d < 16; ++d) a[d] = (d0 + d < W) ? g.fs * (float(c[d]) - h) : 0.f;
 #pragma unroll
-        for (int d = 0; d < 16; ++d) Areg[d] = a[d];
-        float* bd = &Bs[buf][qq * ESTR + qd];
-        *reinterpret_cast<float4*>(bd) = make_float4(g.q[0], g.q[1], g.q[2], g.q[3]);
-        *reinterpret_cast<float4*>(bd + 4) = make_float4(g.q[4], g.q[5], g.q[6], g.q[7]);
+        for (int m = 0; m < 2; ++m) {
+            uint32_t t0[4], t1[4], t2[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) split3(a[8 * m + 2 * k], a[8 * m + 2 * k + 1], t0[k], t1[k], t2[k]);
+            Areg[0][m] = u32x4{t0[0], t0[1], t0[2], t0[3]};
+            Areg[1][m] = u32x4{t1[0], t1[1], t1[2], t1[3]};
+            Areg[2][m] = u32x4{t2[0], t2[1], t2[2], t2[3]};
+        }
+#pragma unroll
+        for (int tm = 0; tm < 3; ++tm) *bq(buf, tm, qq, qd) = g.q[tm];
     };
 
     floatx16 acc[2];
@@ -1342,25 +1367,23 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
             const bool more = s1 < n_kept;
             if (more) fetch(g, s1, j1);
-            const float* b0 = &Bs[buf][li * ESTR + lh * 16];
-            const float* b1 = b0 + 32 * ESTR;
-            float A[16], B0[16], B1[16];
+            // per half m: the six products of the split terms, smallest first
+            // (the projection's scheme), against queries li and 32 + li
+            constexpr int TA[6] = {2, 1, 0, 1, 0, 0};
+            constexpr int TB[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-            for (int d = 0; d < 16; ++d) A[d] = Areg[d];
+            for (int m = 0; m < 2; ++m) {
+                u32x4 B0[3], B1[3];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float4 vb0 = *reinterpret_cast<const float4*>(b0 + 4 * q);
-                B0[4 * q] = vb0.x; B0[4 * q + 1] = vb0.y; B0[4 * q + 2] = vb0.z; B0[4 * q + 3] = vb0.w;
-                if (QB == 2) {
-                    const float4 vb1 = *reinterpret_cast<const float4*>(b1 + 4 * q);
-                    B1[4 * q] = vb1.x; B1[4 * q + 1] = vb1.y; B1[4 * q + 2] = vb1.z; B1[4 * q + 3] = vb1.w;
+                for (int tm = 0; tm < 3; ++tm) {
+                    B0[tm] = *bq(buf, tm, li, 16 * lh + 8 * m);
+                    if (QB == 2) B1[tm] = *bq(buf, tm, 32 + li, 16 * lh + 8 * m);
                 }
-            }
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B0[j], acc[0], 0, 0, 0);
-                if (QB == 2)
-                    acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(A[j], B1[j], acc[1], 0, 0, 0);
+                for (int u = 0; u < 6; ++u) {
+                    acc[0] = mfma_bf16(Areg[TA[u]][m], B0[TB[u]], acc[0]);
+                    if (QB == 2) acc[1] = mfma_bf16(Areg[TA[u]][m], B1[TB[u]], acc[1]);
+                }
             }
             if (!more) break;
             put(g, s1, j1, buf ^ 1);
@@ -1470,6 +1493,33 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         }
     }
 }
+
+// The scan's queries as exact three-term bf16 splits, once per scan rather
+// than once per record tile: query q, kept dims 8 g .. 8 g + 7 at
+// Qs[(q qg + g) 3 + term] (16 bytes per term); dims past D_kept are zero.
+__global__ __launch_bounds__(256) void split_query_kernel(const float* __restrict__ Qp, int nq,
+                                                          int dk, int qg, u32x4* __restrict__ Qs) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(nq) * qg) return;
+    const int64_t q = idx / qg;
+    const int g = int(idx - q * qg);
+    float v[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int j = 8 * g + d;
+        v[d] = j < dk ? Qp[q * dk + j] : 0.f;
+    }
+    uint32_t t0[4], t1[4], t2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) split3(v[2 * k], v[2 * k + 1], t0[k], t1[k], t2[k]);
+    Qs[idx * 3 + 0] = u32x4{t0[0], t0[1], t0[2], t0[3]};
+    Qs[idx * 3 + 1] = u32x4{t1[0], t1[1], t1[2], t1[3]};
+    Qs[idx * 3 + 2] = u32x4{t2[0], t2[1], t2[2], t2[3]};
+}
+
+// 8-dim query groups the split covers: the kept dims and the 32 more a
+// segment's last k-step can read past D_kept
+inline int query_groups(int dk) { return (dk + 7) / 8 + 4; }
 
 // sigma_s of Section 4.3 for query blockIdx.y and kept segment blockIdx.x:
 // ||S_s q'_s||, the standard deviation over the data of <o_s, q_s>.  The
@@ -2027,8 +2077,11 @@ int64_t saq_estimate_workspace_bytes(const saq_plan* p, int32_t nq) {
     const int64_t q = std::max(nq, 1);
     // Qp [nq x D_kept], ||q - c||^2 [nq], the row-block sums of squares
     // behind sigma [nq x n_kept x 8], stage bounds and segment sums of q'
-    // [nq x n_kept] each
-    return q * std::max(p->D_kept, 1) * 4 + q * 4 + (8 + 2) * q * std::max(p->n_kept, 1) * 4 + 512;
+    // [nq x n_kept] each, then (16-byte aligned) the three-term bf16 split of
+    // the queries [nq x query_groups x 3 x 16 bytes]
+    const int64_t dk = std::max(p->D_kept, 1);
+    return q * dk * 4 + q * 4 + (8 + 2) * q * std::max(p->n_kept, 1) * 4 + 16 +
+           q * query_groups(int(dk)) * 48 + 512;
 }
 
 }  // extern "C"
@@ -2046,19 +2099,22 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
     float* Qp = reinterpret_cast<float*>(base);
-    float* qn2 = Qp + int64_t(nq) * std::max(p->D_kept, 1);
-    saq_status s = launch_project(p, Q, nq, Qp, std::max(p->D_kept, 1), LAYOUT_ROWS, qn2, st,
-                                  RefRows{ref, nullptr, 1});
+    const int dk = std::max(p->D_kept, 1), qg = query_groups(dk);
+    float* qn2 = Qp + int64_t(nq) * dk;
+    u32x4* Qs = reinterpret_cast<u32x4*>((reinterpret_cast<uintptr_t>(qn2 + nq) + 15) & ~uintptr_t(15));
+    saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st, RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
+    hipLaunchKernelGGL(split_query_kernel, dim3(unsigned((int64_t(nq) * qg + 255) / 256)), dim3(256), 0,
+                       st, Qp, nq, dk, qg, Qs);
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
     if (nq <= 32)
-        hipLaunchKernelGGL((estimate_kernel<false, 1>), grid, dim3(256), 0, st, Qp, nq,
-                           std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
-                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out);
+        hipLaunchKernelGGL((estimate_kernel<false, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
+                           nullptr, nullptr, nullptr, nullptr, out, Qs, qg);
     else
-        hipLaunchKernelGGL((estimate_kernel<false, 2>), grid, dim3(256), 0, st, Qp, nq,
-                           std::max(p->D_kept, 1), qn2, dev_seg(p), p->n_kept, codes, p->code_bytes,
-                           factors, n, int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out);
+        hipLaunchKernelGGL((estimate_kernel<false, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
+                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
+                           nullptr, nullptr, nullptr, nullptr, out, Qs, qg);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
@@ -2091,8 +2147,13 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     float* sig = qn2 + nq;                                 // [nq][n_kept][SIG_RB]
     float* lbq = sig + int64_t(nq) * p->n_kept * SIG_RB;
     float* qsum = lbq + int64_t(nq) * p->n_kept;
+    const int qg = query_groups(dk);
+    u32x4* Qs = reinterpret_cast<u32x4*>((reinterpret_cast<uintptr_t>(qsum + int64_t(nq) * p->n_kept) + 15) &
+                                         ~uintptr_t(15));
     saq_status s = launch_project(p, Q, nq, Qp, dk, LAYOUT_ROWS, qn2, st, RefRows{ref, nullptr, 1});
     if (s != SAQ_OK) return s;
+    hipLaunchKernelGGL(split_query_kernel, dim3(unsigned((int64_t(nq) * qg + 255) / 256)), dim3(256), 0,
+                       st, Qp, nq, dk, qg, Qs);
     hipLaunchKernelGGL(sigma_kernel, dim3(unsigned(p->n_kept), unsigned(nq), SIG_RB), dim3(256), 0, st, Qp, dk,
                        dev_seg(p), p->n_kept, dev_S(p), sig, qsum);
     hipError_t e = hipGetLastError();
@@ -2105,11 +2166,11 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     if (nq <= 32)
         hipLaunchKernelGGL((estimate_kernel<true, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
                            dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
-                           stage, out);
+                           stage, out, Qs, qg);
     else
         hipLaunchKernelGGL((estimate_kernel<true, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
                            dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
-                           stage, out);
+                           stage, out, Qs, qg);
     e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }
