@@ -967,7 +967,7 @@ constexpr int EROW = EK + 8;
 constexpr int EST_LDS_FLOATS = 2 * 3 * EQ * EROW / 2;  // 30,720 bytes
 // open pairs at which a multi-stage tile leaves the matrix cores; two lists
 // of this many (key, partial sum) entries reuse the query-slice LDS
-constexpr int EMS_CAP = 512;
+constexpr int EMS_CAP = 256;
 constexpr int EMS_LANES = 8;    // lanes per open pair in the sparse finish
 static_assert(2 * EMS_CAP * 2 <= EST_LDS_FLOATS, "pair lists must fit the query-slice LDS");
 
