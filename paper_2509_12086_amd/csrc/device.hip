@@ -923,15 +923,21 @@ __global__ __launch_bounds__(256, 2) void fused_encode_kernel(const FusedArgs ar
 // D_kept values per record, and the projected queries q'.  A workgroup takes
 // 128 records x 64 queries; a k-step covers 32 kept dims of one segment.
 // Each k-step's raw inputs (16 dims of every bit plane of one record per
-// lane, 8 query values per thread, the record's f_s) are fetched one k-step
-// ahead.  After the current k-step's MFMAs each lane unpacks its 16 dims as
-// FP32 f_s (c - (2^B - 1)/2) straight into its own A operand registers
-// (wave w holds records 32w .. 32w + 31), and the queries go to LDS, the
-// only operand the four waves share; each wave then runs 2 x 16
-// v_mfma_f32_32x32x2_f32 against all 64 queries.  A segment whose width is
-// not a multiple of 32 pads its last k-step with zeros on the record side.  Segments of at most 8 bits unpack a
-// plane byte (8 dims) with one lookup in a 256-entry table that spreads its
-// bits to one bit per byte.  With prefix b > 0 a segment reads only its
+// lane, 8 query dims per thread as three bf16 terms, the record's f_s) are
+// fetched one k-step ahead.  After the current k-step's MFMAs each lane
+// unpacks its 16 dims as FP32 f_s (c - (2^B - 1)/2), splits them exactly
+// into three bf16 terms straight into its own A operand registers (wave w
+// holds records 32w .. 32w + 31), and the query terms go to LDS, the only
+// operand the four waves share.  Each FP32 product is then formed as the
+// projection forms it, from the six products a_i q_j with i + j <= 2 of
+// the exact splits, accumulated in FP32: per 16-dim half and 32-query block
+// six v_mfma_f32_32x32x16_bf16 (24 per wave and k-step with two blocks).
+// The queries are split once per scan (split_query_kernel) when a
+// segment's first kept column is a multiple of 8, else while staging.  A
+// segment whose width is not a multiple of 32 pads its last k-step with
+// zeros on the record side.  Segments of at most 8 bits unpack a plane
+// byte (8 dims) with one lookup in a 256-entry table that spreads its bits
+// to one bit per byte.  With prefix b > 0 a segment reads only its
 // first min(b, B) bit planes, the b-bit prefix floor(c / 2^(B-b)) of every
 // code, and scales its factor by 2^(B-b) (progressive approximation).
 //
@@ -1065,8 +1071,8 @@ __device__ __forceinline__ float pair_segment_any(int B, const uint8_t* __restri
     }
 }
 
-// Occupancy: the plain scan fits 4 waves per SIMD without spilling (100
-// VGPRs), the multi-stage variant 3 (its bound state needs about 150).
+// Occupancy: the plain scan fits 4 waves per SIMD (about 127 VGPRs), the
+// multi-stage variant 3 (its bound state and lists need up to 168).
 // QB: 32-query MFMA blocks per tile, 2, or 1 when at most 32 queries are
 // scanned (the second block would be all padding).
 template <bool MS, int QB>
