@@ -115,10 +115,24 @@ saq_status saq_covariance(const float* X_dev, int64_t n, int32_t D, int64_t fit_
                           double* mean_dev, double* cov_dev, void* ws_dev, int64_t ws_bytes,
                           void* stream);
 
-/* saq_fit_plan with the mean and covariance from saq_covariance: the rows
-   stay on the device, the D x D covariance is copied back (the call waits
-   for `stream`), and the eigen-decomposition and plan search run on the
-   host as in saq_fit_plan.  ws_dev: saq_fit_workspace_bytes bytes. */
+/* Eigen-decomposition of a symmetric matrix on the device (the PCA basis
+   of Section 4.1 from a covariance): A_dev [n x n] FP64 row-major (read
+   only; the upper and lower triangles must agree), w_dev [n] the
+   eigenvalues in no particular order, V_dev [n x n] FP64 row-major with the
+   unit eigenvector of w_dev[j] in column j.  Cyclic Jacobi with a parallel
+   (round-robin) ordering, in FP64, run until the off-diagonal mass is below
+   1e-15 of the diagonal's; SAQ_EINVAL if that takes more than 40 sweeps.
+   The call waits for `stream` once per sweep.  ws_dev:
+   saq_sym_eigen_workspace_bytes(n) bytes (three n x n FP64 buffers). */
+int64_t    saq_sym_eigen_workspace_bytes(int32_t n);
+saq_status saq_sym_eigen_device(const double* A_dev, int32_t n, double* w_dev, double* V_dev,
+                                void* ws_dev, int64_t ws_bytes, void* stream);
+
+/* saq_fit_plan with the rows on the device: the mean and covariance from
+   saq_covariance, their eigen-decomposition from saq_sym_eigen_device, then
+   the basis (D + D x D values) is copied back (the call waits for `stream`)
+   and the plan search runs on the host, as saq_plan_from_basis.
+   ws_dev: saq_fit_workspace_bytes bytes. */
 int64_t    saq_fit_workspace_bytes(int64_t n, int32_t D, const saq_plan_params* p);
 saq_status saq_fit_plan_device(const float* X_dev, int64_t n, int32_t D,
                                const saq_plan_params* p, void* ws_dev, int64_t ws_bytes,

@@ -59,6 +59,7 @@ EXPORTS = ("saq_default_params", "saq_fit_plan", "saq_plan_from_basis", "saq_pla
            "saq_estimate_multistage", "saq_covariance_workspace_bytes", "saq_covariance",
            "saq_encode_ref", "saq_estimate_dist_ref", "saq_estimate_multistage_ref",
            "saq_fit_workspace_bytes", "saq_fit_plan_device",
+           "saq_sym_eigen_workspace_bytes", "saq_sym_eigen_device",
            "saq_encode_batched_workspace_bytes",
            "saq_encode_batched", "saq_encode_noalloc", "saq_last_error", "saq_version")
 
@@ -124,6 +125,8 @@ def lib() -> ctypes.CDLL:
         "saq_covariance": (i32, [P, i64, i32, i64, P, P, P, i64, P]),
         "saq_fit_workspace_bytes": (i64, [i64, i32, P]),
         "saq_fit_plan_device": (i32, [P, i64, i32, P, P, i64, P, P]),
+        "saq_sym_eigen_workspace_bytes": (i64, [i32]),
+        "saq_sym_eigen_device": (i32, [P, i32, P, P, P, i64, P]),
         "saq_encode_batched_workspace_bytes": (i64, [P, i32, P]),
         "saq_encode_batched": (i32, [P, i32, i32, P, P, i64, P]),
         "saq_encode_noalloc": (i32, [P, P, i64, i32, P, P, P]),
@@ -540,6 +543,29 @@ def covariance(X, fit_sample: int = 0, mean=None, cov=None, workspace=None, stre
                                 _dev_ptr(workspace), workspace.numel() * workspace.element_size(),
                                 _stream_ptr(stream, X.device)))
     return mean, cov
+
+
+def sym_eigen(A, w=None, V=None, workspace=None, stream=None):
+    """saq_sym_eigen_device: (eigenvalues f64 [n], eigenvectors f64 [n, n],
+    eigenvector j in column j) of the symmetric CUDA float64 matrix A."""
+    torch = _torch()
+    if not (A.is_cuda and A.dtype == torch.float64 and A.is_contiguous() and A.dim() == 2
+            and A.shape[0] == A.shape[1]):
+        raise ValueError("A must be a square contiguous CUDA float64 tensor")
+    n = A.shape[0]
+    if w is None:
+        w = torch.empty(n, dtype=torch.float64, device=A.device)
+    if V is None:
+        V = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    need = int(lib().saq_sym_eigen_workspace_bytes(n))
+    if need < 0:
+        raise ValueError("bad size")
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=A.device)
+    _check(lib().saq_sym_eigen_device(_dev_ptr(A), n, _dev_ptr(w), _dev_ptr(V), _dev_ptr(workspace),
+                                      workspace.numel() * workspace.element_size(),
+                                      _stream_ptr(stream, A.device)))
+    return w, V
 
 
 def unpack_codes(plan: Plan, packed: np.ndarray) -> np.ndarray:

@@ -14,6 +14,19 @@
 //   cov_reduce_kernel
 //       adds the row slices of each element in slice order, divides by m and
 //       writes both triangles.
+//   jacobi_*_kernel
+//       the covariance's eigen-decomposition (the PCA basis of Section 4.1)
+//       by the cyclic Jacobi method with a parallel ordering: in each round
+//       the indices form n/2 disjoint pairs (the round-robin tournament
+//       schedule), one plane rotation per pair zeroes that pair's
+//       off-diagonal entry, and the rotations of a round commute, so
+//       A <- J^T A J and V <- V J are applied at once: each thread takes one
+//       2 x 2 block (pair P rows, pair Q columns) of A, B' = R_P^T B R_Q,
+//       from one buffer into the other, and the 2 x 2 block of V in place.
+//       n - 1 rounds make a sweep; sweeps repeat until the off-diagonal
+//       mass is below FP64 rounding of the diagonal (Jacobi 1846; the
+//       parallel ordering of Brent and Luk 1985; the rotation formulas of
+//       Rutishauser, Numer. Math. 9, 1966).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -193,6 +206,140 @@ __global__ __launch_bounds__(256) void cov_reduce_kernel(const double* __restric
     cov[int64_t(j) * D + i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Cyclic Jacobi on the device.  N is n rounded up to even; a padded index
+// has a zero row and column, so its rotations are the identity and its
+// column of V stays a unit vector outside the first n rows and columns.
+// ---------------------------------------------------------------------------
+// the pair k (k < N/2) of round r of the round-robin schedule on N players:
+// player N - 1 stays, the others rotate
+__device__ __forceinline__ void jacobi_pair(int N, int r, int k, int& a, int& b) {
+    if (k == 0) {
+        a = r;
+        b = N - 1;
+    } else {
+        const int m = N - 1;
+        a = (r + k) % m;
+        b = (r - k + m) % m;
+    }
+    if (a > b) {
+        const int t = a;
+        a = b;
+        b = t;
+    }
+}
+
+// (c, s) of R = [[c, s], [-s, c]] with (R^T [[app, apq], [apq, aqq]] R)[0][1] = 0,
+// the smaller of the two angles
+__device__ __forceinline__ void jacobi_rotation(double app, double aqq, double apq, double& c,
+                                                double& s) {
+    if (apq == 0.0) {
+        c = 1.0;
+        s = 0.0;
+        return;
+    }
+    const double th = (aqq - app) / (2.0 * apq);
+    double t;
+    if (fabs(th) > 1e150) {
+        t = 0.5 / th;
+    } else {
+        t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
+        if (th < 0.0) t = -t;
+    }
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+}
+
+__global__ __launch_bounds__(256) void jacobi_init_kernel(const double* __restrict__ C, int n, int N,
+                                                          double* __restrict__ A,
+                                                          double* __restrict__ V) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(N) * N) return;
+    const int i = int(idx / N), j = int(idx % N);
+    A[idx] = (i < n && j < n) ? C[int64_t(i) * n + j] : 0.0;
+    V[idx] = i == j ? 1.0 : 0.0;
+}
+
+// one round: thread (kp, kq) maps block (pair kp rows, pair kq columns) of
+// Ain into Aout, and rotates columns of pair kq in rows of pair kp of V
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const double* __restrict__ Ain,
+                                                           double* __restrict__ Aout,
+                                                           double* __restrict__ V, int N, int r) {
+    const int h = N / 2;
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(h) * h) return;
+    const int kp = int(idx / h), kq = int(idx % h);
+    int p0, p1, q0, q1;
+    jacobi_pair(N, r, kp, p0, p1);
+    jacobi_pair(N, r, kq, q0, q1);
+    auto at = [&](int i, int j) { return Ain[int64_t(i) * N + j]; };
+    double cp, sp, cq, sq;
+    jacobi_rotation(at(p0, p0), at(p1, p1), at(p0, p1), cp, sp);
+    jacobi_rotation(at(q0, q0), at(q1, q1), at(q0, q1), cq, sq);
+    const double b00 = at(p0, q0), b01 = at(p0, q1), b10 = at(p1, q0), b11 = at(p1, q1);
+    // rows: R_P^T B
+    const double r00 = cp * b00 - sp * b10, r01 = cp * b01 - sp * b11;
+    const double r10 = sp * b00 + cp * b10, r11 = sp * b01 + cp * b11;
+    // columns: (R_P^T B) R_Q
+    double n00 = r00 * cq - r01 * sq, n01 = r00 * sq + r01 * cq;
+    double n10 = r10 * cq - r11 * sq, n11 = r10 * sq + r11 * cq;
+    if (kp == kq) n01 = n10 = 0.0;   // the pair's own entry, zero by construction
+    Aout[int64_t(p0) * N + q0] = n00;
+    Aout[int64_t(p0) * N + q1] = n01;
+    Aout[int64_t(p1) * N + q0] = n10;
+    Aout[int64_t(p1) * N + q1] = n11;
+    // V <- V R_Q on rows p0, p1 (every row belongs to exactly one pair)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int64_t row = int64_t(e ? p1 : p0) * N;
+        const double v0 = V[row + q0], v1 = V[row + q1];
+        V[row + q0] = v0 * cq - v1 * sq;
+        V[row + q1] = v0 * sq + v1 * cq;
+    }
+}
+
+// per-block sums of squares: off-diagonal entries, diagonal entries
+__global__ __launch_bounds__(256) void jacobi_off_kernel(const double* __restrict__ A, int N,
+                                                         double* __restrict__ part) {
+    __shared__ double so[256], sd[256];
+    double off = 0.0, dg = 0.0;
+    for (int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x; idx < int64_t(N) * N;
+         idx += int64_t(gridDim.x) * 256) {
+        const double a = A[idx];
+        if (idx / N == idx % N) dg += a * a;
+        else off += a * a;
+    }
+    so[threadIdx.x] = off;
+    sd[threadIdx.x] = dg;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) {
+            so[threadIdx.x] += so[threadIdx.x + w];
+            sd[threadIdx.x] += sd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = so[0];
+        part[2 * blockIdx.x + 1] = sd[0];
+    }
+}
+
+// w[j] = A[j][j], Vout = the first n rows and columns of V
+__global__ __launch_bounds__(256) void jacobi_finish_kernel(const double* __restrict__ A,
+                                                            const double* __restrict__ V, int n,
+                                                            int N, double* __restrict__ w,
+                                                            double* __restrict__ Vout) {
+    const int64_t idx = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (idx >= int64_t(n) * n) return;
+    const int i = int(idx / n), j = int(idx % n);
+    Vout[idx] = V[int64_t(i) * N + j];
+    if (i == j) w[i] = A[int64_t(i) * N + i];
+}
+
+constexpr int JACOBI_OFF_BLOCKS = 256;
+constexpr int JACOBI_MAX_SWEEPS = 40;
+
 struct CovShape {
     int64_t m = 0, nb = 0, slice_rows = 0;
     int nt = 0, tiles = 0, slices = 0;
@@ -250,8 +397,66 @@ saq_status run_covariance(const float* X, int64_t n, int32_t D, int64_t fit_samp
     return e == hipSuccess ? SAQ_OK : hip_err(e, "cov_reduce_kernel launch");
 }
 
-// the fit's own buffers ahead of the covariance workspace: mean, covariance
-int64_t fit_extra(int32_t D) { return align256(int64_t(D) * 8) + align256(int64_t(D) * D * 8); }
+int64_t jacobi_bytes(int32_t n) {
+    const int64_t N = n + (n & 1);
+    return 3 * align256(N * N * 8) + align256(int64_t(JACOBI_OFF_BLOCKS) * 2 * 8) + 256;
+}
+
+// eigen-decomposition of the symmetric C [n x n] (device): w [n] in the
+// Jacobi order, V [n x n] row-major with eigenvector j in column j; waits
+// for `st` once per sweep (the convergence test)
+saq_status run_jacobi(const double* C, int32_t n, double* w, double* V, void* ws, int64_t ws_bytes,
+                      hipStream_t st) {
+    if (ws_bytes < jacobi_bytes(n)) return saq::fail(SAQ_EINVAL, "workspace too small");
+    const int N = n + (n & 1);
+    const int64_t el = int64_t(N) * N;
+    char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+    double* A[2] = {reinterpret_cast<double*>(base), reinterpret_cast<double*>(base + align256(el * 8))};
+    double* Vw = reinterpret_cast<double*>(base + 2 * align256(el * 8));
+    double* part = reinterpret_cast<double*>(base + 3 * align256(el * 8));
+    const unsigned gel = unsigned((el + 255) / 256);
+    const unsigned gpair = unsigned((int64_t(N / 2) * (N / 2) + 255) / 256);
+    hipLaunchKernelGGL(jacobi_init_kernel, dim3(gel), dim3(256), 0, st, C, n, N, A[0], Vw);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_err(e, "jacobi_init_kernel launch");
+    std::vector<double> hp(size_t(JACOBI_OFF_BLOCKS) * 2);
+    int cur = 0;
+    bool converged = false;
+    for (int sweep = 0; sweep < JACOBI_MAX_SWEEPS && !converged; ++sweep) {
+        for (int r = 0; r + 1 < N; ++r) {
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(gpair), dim3(256), 0, st, A[cur], A[cur ^ 1],
+                               Vw, N, r);
+            cur ^= 1;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_err(e, "jacobi_round_kernel launch");
+        hipLaunchKernelGGL(jacobi_off_kernel, dim3(JACOBI_OFF_BLOCKS), dim3(256), 0, st, A[cur], N, part);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, hp.size() * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_err(e, "jacobi convergence test");
+        double off = 0.0, dg = 0.0;
+        for (int b = 0; b < JACOBI_OFF_BLOCKS; ++b) {
+            off += hp[2 * b];
+            dg += hp[2 * b + 1];
+        }
+        // below FP64 rounding of the diagonal: further rotations change
+        // nothing in the eigenvalues' leading 15 digits
+        converged = off <= 1e-30 * dg;
+    }
+    if (!converged) return saq::fail(SAQ_EINVAL, "Jacobi eigen-decomposition did not converge");
+    hipLaunchKernelGGL(jacobi_finish_kernel, dim3(unsigned((int64_t(n) * n + 255) / 256)), dim3(256), 0,
+                       st, A[cur], Vw, n, N, w, V);
+    e = hipGetLastError();
+    return e == hipSuccess ? SAQ_OK : hip_err(e, "jacobi_finish_kernel launch");
+}
+
+// the fit's own buffers ahead of the covariance workspace: mean,
+// covariance, eigenvalues, eigenvectors, then the Jacobi workspace
+int64_t fit_extra(int32_t D) {
+    return align256(int64_t(D) * 8) + align256(int64_t(D) * D * 8) + align256(int64_t(D) * 8) +
+           align256(int64_t(D) * D * 8) + jacobi_bytes(D);
+}
 
 }  // namespace
 
@@ -271,6 +476,18 @@ saq_status saq_covariance(const float* X_dev, int64_t n, int32_t D, int64_t fit_
                           static_cast<hipStream_t>(stream));
 }
 
+int64_t saq_sym_eigen_workspace_bytes(int32_t n) {
+    if (n <= 0) return -1;
+    return jacobi_bytes(n);
+}
+
+saq_status saq_sym_eigen_device(const double* A_dev, int32_t n, double* w_dev, double* V_dev,
+                                void* ws_dev, int64_t ws_bytes, void* stream) {
+    if (n <= 0) return saq::fail(SAQ_EINVAL, "bad size");
+    if (!A_dev || !w_dev || !V_dev || !ws_dev) return saq::fail(SAQ_EINVAL, "null buffer");
+    return run_jacobi(A_dev, n, w_dev, V_dev, ws_dev, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
 int64_t saq_fit_workspace_bytes(int64_t n, int32_t D, const saq_plan_params* p) {
     if (!p || n <= 0 || D <= 0 || p->fit_sample < 0) return -1;
     return fit_extra(D) + cov_shape(n, D, p->fit_sample).bytes + 256;
@@ -283,20 +500,29 @@ saq_status saq_fit_plan_device(const float* X_dev, int64_t n, int32_t D, const s
     if (ws_bytes < saq_fit_workspace_bytes(n, D, p)) return saq::fail(SAQ_EINVAL, "workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
     char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws_dev) + 255) & ~uintptr_t(255));
+    const int64_t dv = align256(int64_t(D) * 8), dm = align256(int64_t(D) * D * 8);
     double* mu = reinterpret_cast<double*>(base);
-    double* cov = reinterpret_cast<double*>(base + align256(int64_t(D) * 8));
+    double* cov = reinterpret_cast<double*>(base + dv);
+    double* w = reinterpret_cast<double*>(base + dv + dm);
+    double* V = reinterpret_cast<double*>(base + 2 * dv + dm);
+    char* jws = base + 2 * dv + 2 * dm;
     char* rest = base + fit_extra(D);
     const int64_t rest_bytes = ws_bytes - (rest - static_cast<char*>(ws_dev));
     saq_status s = run_covariance(X_dev, n, D, p->fit_sample, mu, cov, rest, rest_bytes, st);
     if (s != SAQ_OK) return s;
+    s = run_jacobi(cov, D, w, V, jws, jacobi_bytes(D), st);
+    if (s != SAQ_OK) return s;
     try {
-        std::vector<double> hm(static_cast<size_t>(D)), hc(static_cast<size_t>(D) * D);
+        std::vector<double> hm(static_cast<size_t>(D)), hw(static_cast<size_t>(D)),
+            hv(static_cast<size_t>(D) * D);
         hipError_t e = hipMemcpyAsync(hm.data(), mu, size_t(D) * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hw.data(), w, size_t(D) * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(hc.data(), cov, size_t(D) * D * 8, hipMemcpyDeviceToHost, st);
+            e = hipMemcpyAsync(hv.data(), V, size_t(D) * D * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_err(e, "copying the moments to the host");
-        return saq::plan_from_moments(D, hm, hc, *p, out);
+        if (e != hipSuccess) return hip_err(e, "copying the basis to the host");
+        // the plan search on the host, from the device's basis (sorted there)
+        return saq_plan_from_basis(hm.data(), hv.data(), hw.data(), D, p, out);
     } catch (const std::bad_alloc&) {
         return saq::fail(SAQ_ENOMEM, "out of host memory");
     }

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synth
 import paper_2509_12086_amd as saq
-from gpu_util import say, to_dev
+from gpu_util import cuda, say, to_dev
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -114,3 +114,57 @@ def test_full_size_fit_sample(D):
         ref = oracle.plan_search(lam, 4.0, params.granularity, params.max_bits, params.max_width)
         assert p.widths == ref.widths and p.bits == ref.bits
         np.testing.assert_allclose(p.arrays()[2], lam, rtol=1e-9, atol=1e-12 * lam[0])
+
+
+def _eig_checks(A, w, V, label, tol=1e-12):
+    """Eigenvalues against numpy's (LAPACK) on the same matrix, the residual
+    A V - V diag(w) and the orthogonality of V, all relative to max |A|."""
+    n = A.shape[0]
+    scale = max(np.max(np.abs(A)), 1e-300)
+    ref = np.linalg.eigvalsh(A)
+    ew = np.max(np.abs(np.sort(w) - ref)) / scale
+    res = np.max(np.abs(A @ V - V * w[None, :])) / scale
+    orth = np.max(np.abs(V.T @ V - np.eye(n)))
+    say(f"  {label}: n={n} eigenvalues {ew:.1e} residual {res:.1e} orthogonality {orth:.1e}")
+    assert ew < tol and res < tol and orth < tol, label
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 333])
+def test_sym_eigen_random(n):
+    rng = np.random.default_rng(n)
+    B = rng.standard_normal((n, n))
+    A = (B + B.T) / 2
+    w, V = saq.sym_eigen(torch.from_numpy(A).to(cuda()))
+    torch.cuda.synchronize()
+    _eig_checks(A, w.cpu().numpy(), V.cpu().numpy(), "random symmetric")
+
+
+def test_sym_eigen_special_matrices():
+    """Degenerate cases: zero, diagonal (no rotation needed), repeated
+    eigenvalues (identity plus a rank-one term), and a covariance whose
+    spectrum spans ten orders of magnitude."""
+    rng = np.random.default_rng(3)
+    n = 50
+    u = rng.standard_normal(n)
+    cases = {"zero": np.zeros((n, n)), "diagonal": np.diag(rng.standard_normal(n)),
+             "identity + rank one": np.eye(n) + np.outer(u, u)}
+    X = rng.standard_normal((4000, n)) * np.logspace(0, -5, n)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    cases["wide spectrum"] = Q @ ((X.T @ X) / 4000) @ Q.T
+    cases["wide spectrum"] = (cases["wide spectrum"] + cases["wide spectrum"].T) / 2
+    for label, A in cases.items():
+        w, V = saq.sym_eigen(torch.from_numpy(np.ascontiguousarray(A)).to(cuda()))
+        torch.cuda.synchronize()
+        _eig_checks(A, w.cpu().numpy(), V.cpu().numpy(), label)
+
+
+def test_sym_eigen_of_the_device_covariance():
+    """The fit's own use: the device covariance of the cfg2 shape (20,000 x
+    960) decomposed on the device, against LAPACK on the same matrix."""
+    X = synth.cfg2(20_000).rows()
+    _, cov = saq.covariance(to_dev(X), 0)
+    w, V = saq.sym_eigen(cov)
+    torch.cuda.synchronize()
+    _eig_checks(cov.cpu().numpy(), w.cpu().numpy(), V.cpu().numpy(), "cfg2 covariance", tol=1e-11)
+    with pytest.raises(saq.SaqError, match="SAQ_EINVAL"):
+        saq.sym_eigen(cov, workspace=torch.empty(16, dtype=torch.uint8, device=cov.device))
