@@ -723,8 +723,9 @@ def multistage_timing(plan, Q, codes, fac, plain_out, ws, stream, k, m=4.0, sub=
 def scan_leg(a):
     """Estimate scans (Section 3.2): 64 queries against 1M stored records
     encoded at 4 b/dim, for D = 128, 768, 1536 and 3072 (variance
-    exp(-8i/D)); the scan kernel is an FP32 matrix-core contraction of the
-    records' scaled codes with the projected queries."""
+    exp(-8i/D)); the scan kernel contracts the records' scaled codes with
+    the projected queries on the bf16 matrix cores, each FP32 product formed
+    from six products of exactly split operands."""
     import torch
     import synth
     import paper_2509_12086_amd as saq
@@ -756,6 +757,8 @@ def scan_leg(a):
         flops = 2.0 * nq * plan.D_kept * n
         row = {"D": ds.d, "D_kept": plan.D_kept, "code_bytes": plan.code_bytes,
                "ms_per_scan": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+               "frac_bf16_mfma": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
+               "issued_frac_bf16_mfma": SPLIT_PRODUCTS * flops / (ms * 1e-3) / PEAK_BF16_MFMA,
                "frac_fp32_mfma": flops / (ms * 1e-3) / PEAK_FP32_MFMA,
                "record_GBps": n * (plan.code_bytes + 4 * plan.n_factors) / (ms * 1e-3) / 1e9}
         if ds.d == 3072:
