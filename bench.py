@@ -317,8 +317,9 @@ def kernel_records(a, leg):
     e2e_bytes = n * (4.0 * D + plan.code_bytes + 4.0 * plan.n_factors)
     lane_ops = TRIAL_LANE_OPS * 2.0 * a.rounds * dk       # per vector
     bind = {"hbm": PEAK_HBM / (e2e_bytes / n),
-            "mfma_bf16": PEAK_BF16_MFMA / (flops / n),
-            "valu": VALU_LANE_OPS / lane_ops}
+            "mfma_bf16": PEAK_BF16_MFMA / (flops / n)}
+    if lane_ops > 0:                                      # no trials at --rounds 0
+        bind["valu"] = VALU_LANE_OPS / lane_ops
     bound = min(bind, key=bind.get)
     return {
         "roofline": {
