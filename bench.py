@@ -93,6 +93,33 @@ def recorded_traffic(kernel: str, workload: str):
     return None if k is None else k["read_bytes"] + k["write_bytes"]
 
 
+CLOCK_RECORD = os.path.join(ROOT, "profiles", "encode_1Mx960_b4_clock_occupancy.md")
+
+
+def recorded_cycles(kernel: str, workload: str):
+    """GPU clock cycles per launch of `kernel` (rocprofv3 GRBM_GUI_ACTIVE / 8)
+    and the counter run's other clock figures, under the same conditions as
+    recorded_traffic."""
+    rec = _record(CLOCK_RECORD, "clock-record", workload)
+    return None if rec is None else rec.get("kernels", {}).get(kernel)
+
+
+def clock_figures(rec, ms: float):
+    """The clock a kernel ran at in this run: its recorded cycles per launch
+    (constant for given kernel code and shape) over this run's time per
+    launch; with the matrix-core busy cycles, the fraction of those cycles the
+    matrix cores worked."""
+    if rec is None:
+        return None
+    c = float(rec["cycles_per_launch"])
+    out = {"cycles_per_launch": c, "effective_clock_ghz": c / (ms * 1e-3) / 1e9,
+           "resident_waves_per_cu": rec.get("resident_waves_per_cu"),
+           "source": "profiles/encode_1Mx960_b4_clock_occupancy.md"}
+    if "mfma_busy_cycles_per_launch" in rec:
+        out["mfma_busy_frac_of_cycles"] = rec["mfma_busy_cycles_per_launch"] / 1024 / c
+    return out
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -338,6 +365,7 @@ def kernel_records(a, leg):
             "algorithmic_bytes_per_launch": proj_bytes,
             "avg_ms": proj_ms,
             "frac_of_fp32_mfma_peak": achieved / PEAK_FP32_MFMA,
+            "clock": clock_figures(recorded_cycles("project_kernel", workload), proj_ms),
             "split_emulation": {
                 "note": "matrix-core work issued by the six bf16 products per FP32 product: "
                         "MFMA utilisation, not the method's work",
@@ -358,6 +386,7 @@ def kernel_records(a, leg):
                 "achieved": q_valu * 64 / (quant_ms * 1e-3), "peak": VALU_LANE_OPS,
                 "unit": "lane-ops/s", "frac": q_valu * 64 / (quant_ms * 1e-3) / VALU_LANE_OPS,
                 "instructions_per_launch": q_valu},
+            "clock": clock_figures(recorded_cycles("quantize_kernel", workload), quant_ms),
             "avg_ms": quant_ms,
         },
         "end_to_end": {
