@@ -1,7 +1,7 @@
 """Host side of the benchmark (no GPU needed): its one-GPU contract and its
 link to the committed counter records.
 
-`roofline.traffic` and the VALU figures come from rocprofv3 counter runs kept
+`roofline.traffic`, the VALU figures and the clock figures come from rocprofv3 counter runs kept
 as text under profiles/.  They are reported only while the kernel code is the
 code the counters were taken on, keyed by a digest of the code with comments
 and blanks removed: an edit of comments must keep the digest, any edit of code
@@ -43,7 +43,8 @@ def test_code_edits_change_the_digest():
 def test_records_are_keyed_by_the_code_digest():
     """Each committed record carries a code digest; a record for another
     digest or another workload is not reported."""
-    for path, tag in ((bench.TRAFFIC_RECORD, "traffic-record"), (bench.INSTR_RECORD, "instruction-record")):
+    for path, tag in ((bench.TRAFFIC_RECORD, "traffic-record"), (bench.INSTR_RECORD, "instruction-record"),
+                      (bench.CLOCK_RECORD, "clock-record")):
         text = open(path, encoding="utf-8").read()
         assert f"<!-- {tag} " in text and '"code_sha256": "' in text
         assert bench._record(path, tag, "another workload") is None
@@ -84,3 +85,23 @@ def test_roofline_fractions_price_the_methods_own_work():
     assert e["roofline_vectors_per_s"]["mfma_bf16"] == 2.5e15 / (2.0 * 960 * 864)
     assert e["binding_roofline_vectors_per_s"] == min(e["roofline_vectors_per_s"].values())
     assert abs(e["frac_of_binding"] - n / 12.8e-3 / e["binding_roofline_vectors_per_s"]) < 1e-12
+
+
+def test_clock_figures_follow_the_recorded_cycles():
+    """The effective clock is the recorded cycles per launch over this run's
+    time per launch, and the matrix-core busy fraction is the busy cycles per
+    SIMD (1,024 SIMDs) over those cycles; without a record there is no clock
+    figure, and zero adjustment rounds leave the VALU bound out."""
+    rec = {"cycles_per_launch": 1.6e7, "resident_waves_per_cu": 11.0,
+           "mfma_busy_cycles_per_launch": 1024 * 8.0e6}
+    c = bench.clock_figures(rec, 10.0)
+    assert abs(c["effective_clock_ghz"] - 1.6) < 1e-12
+    assert abs(c["mfma_busy_frac_of_cycles"] - 0.5) < 1e-12
+    assert "mfma_busy_frac_of_cycles" not in bench.clock_figures({"cycles_per_launch": 1e6}, 1.0)
+    assert bench.clock_figures(None, 1.0) is None
+    from types import SimpleNamespace
+    plan = SimpleNamespace(D=960, D_kept=864, code_bytes=480, n_factors=8,
+                           info={"projection_fp64_totals": 0})
+    leg = {"plan": plan, "n": 1000, "bpd": 4.0, "proj_ms": 1.0, "quant_ms": 1.0, "ms_step": 2.0}
+    r = bench.kernel_records(SimpleNamespace(rounds=0), leg)
+    assert "valu" not in r["end_to_end"]["roofline_vectors_per_s"]
