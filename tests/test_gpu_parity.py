@@ -165,10 +165,17 @@ def test_encode_non_multiple_dims_and_rounds():
 
 
 def test_encode_deterministic(cfg1):
+    """Per-vector results are the same on every call and independent of the
+    batch a vector is encoded in: rows encoded alone, or at an offset that is
+    not a multiple of the 64-row tiles, give the same record bytes and
+    factors as inside the full batch."""
     ds, X, plan = cfg1
     a = gpu_encode(plan, X[:3000], 4)
     b = gpu_encode(plan, X[:3000], 4)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    for lo, hi in ((0, 1), (1001, 2500), (2937, 3000), (64, 128)):
+        c = gpu_encode(plan, X[lo:hi], 4)
+        assert np.array_equal(c[0], a[0][lo:hi]) and np.array_equal(c[1], a[1][lo:hi]), (lo, hi)
 
 
 def test_estimate_dist(cfg1):
