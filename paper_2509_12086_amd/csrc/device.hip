@@ -1074,8 +1074,12 @@ __device__ __forceinline__ float pair_segment_any(int B, const uint8_t* __restri
 // Occupancy: the plain scan fits 4 waves per SIMD (about 127 VGPRs), the
 // multi-stage variant 3 (its bound state and lists need up to 168).
 // QB: 32-query MFMA blocks per tile, 2, or 1 when at most 32 queries are
-// scanned (the second block would be all padding).
-template <bool MS, int QB>
+// scanned (the second block would be all padding).  FL: lanes per open pair
+// in the multi-stage sparse finish, EMS_LANES, or 1 for plans whose kept
+// segments are all at most 32 dims (one chunk: the other lanes of a group
+// would idle).  A separate instantiation, so plans with wider segments keep
+// their code and registers unchanged.
+template <bool MS, int QB, int FL = EMS_LANES>
 __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
@@ -1444,8 +1448,8 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     if constexpr (MS) {
         // sparse finish from segment s: list `cur` holds the pairs open at
         // its start (workgroup-uniform count `listed`)
-        // a pair's chunks of 32 dims are shared by EMS_LANES consecutive lanes
-        const int sub = t & (EMS_LANES - 1), grp = t / EMS_LANES;
+        // a pair's chunks of 32 dims are shared by FL consecutive lanes
+        const int sub = t & (FL - 1), grp = t / FL;
         int cur = 0;
         for (int si = s; listed > 0 && si < n_kept; ++si) {
             const SegEntry e = segs[si];
@@ -1471,18 +1475,17 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
                     part[(cur ^ 1) * EMS_CAP + slot] = acc;
                 }
             };
-            constexpr int G = 256 / EMS_LANES;     // lane groups
+            constexpr int G = 256 / FL;            // lane groups
             for (int k = grp; k < listed; k += G) {
                 const uint32_t key = keys[cur * EMS_CAP + k];
                 const int q = q0 + int(key >> 8);
                 const int64_t i = r0 + int(key & 255u);
                 float S = pair_segment_any(e.bits, codes + i * code_bytes + e.code_off, e.width,
-                                           Qp + int64_t(q) * dk + e.col, qvec, spread, sub,
-                                           EMS_LANES);
+                                           Qp + int64_t(q) * dk + e.col, qvec, spread, sub, FL);
                 // the group's lanes are consecutive: a butterfly leaves the
                 // pair's sum in all of them
 #pragma unroll
-                for (int o = 1; o < EMS_LANES; o <<= 1) S += __shfl_xor(S, o);
+                for (int o = 1; o < FL; o <<= 1) S += __shfl_xor(S, o);
                 if (sub != 0) continue;
                 const float* fi = factors + i * (n_kept + 1);
                 const float acc = part[cur * EMS_CAP + k] +
@@ -2169,14 +2172,19 @@ static saq_status multistage_impl(const saq_plan* p, const float* Q, int32_t nq,
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "stage_bound_kernel launch");
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
-    if (nq <= 32)
-        hipLaunchKernelGGL((estimate_kernel<true, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
-                           stage, out, Qs, qg);
-    else
-        hipLaunchKernelGGL((estimate_kernel<true, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau,
-                           stage, out, Qs, qg);
+    // one lane per open pair in the sparse finish when every kept segment is
+    // a single 32-dim chunk
+    const bool narrow = p->max_kept_w <= 32;
+#define SAQ_LAUNCH_MS(QB, FL)                                                                     \
+    hipLaunchKernelGGL((estimate_kernel<true, QB, FL>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,  \
+                       dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, 0, lbq, qsum, tau, \
+                       stage, out, Qs, qg)
+    if (nq <= 32) {
+        if (narrow) SAQ_LAUNCH_MS(1, 1); else SAQ_LAUNCH_MS(1, EMS_LANES);
+    } else {
+        if (narrow) SAQ_LAUNCH_MS(2, 1); else SAQ_LAUNCH_MS(2, EMS_LANES);
+    }
+#undef SAQ_LAUNCH_MS
     e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }

@@ -183,6 +183,32 @@ def test_multistage_ragged_widths():
         assert (st < len(plan.kept_widths)).mean() > 0.3
 
 
+def test_multistage_narrow_segments():
+    """A plan whose kept segments are all at most 32 dims (one 32-dim chunk
+    each) runs the sparse finish with one lane per open pair: ragged widths
+    below 32, 1- to 11-bit codes, 1, 3 and 70 queries."""
+    rng = np.random.default_rng(31)
+    widths, bits = [32, 7, 24, 13, 31, 16, 5], [11, 8, 6, 4, 3, 2, 0]
+    D = sum(widths)
+    kept = sum(w for w, b in zip(widths, bits) if b > 0)
+    sd = np.concatenate([np.full(w, v) for w, v in zip(widths, (3.0, 2.2, 1.5, 1.0, 0.7, 0.5, 0.2))])
+    Mw = np.eye(D, dtype=np.float32)[:kept]
+    plan = saq.Plan.from_parts(widths, bits, Mw, np.zeros(D, np.float32), variances=sd ** 2).upload(0)
+    assert max(plan.kept_widths) <= 32
+    X = (rng.standard_normal((2003, D)) * sd).astype(np.float32)
+    packed, fac, codes = oracle_records(plan, X, 4)
+    S = dict(plan=plan, P=np.eye(D)[:kept], lam=(sd ** 2)[:kept], packed=packed, fac=fac,
+             codes=codes)
+    M, c, _ = plan.arrays()
+    for nq, m in ((1, 4.0), (3, 2.0), (70, 4.0)):
+        Q = (rng.standard_normal((nq, D)) * sd).astype(np.float32)
+        plain = oracle.estimate(Q, M, c, plan.kept_widths, plan.kept_bits, codes,
+                                fac[:, :-1].astype(np.float64), fac[:, -1].astype(np.float64))
+        tau = np.sort(plain, axis=1)[:, 9]
+        st, _ = _check(S, Q, m, tau, f"narrow segments nq={nq}")
+        assert (st < len(plan.kept_widths)).mean() > 0.3
+
+
 def test_multistage_argument_errors(gauss):
     S = gauss
     plan = S["plan"]
