@@ -1078,8 +1078,10 @@ __device__ __forceinline__ float pair_segment_any(int B, const uint8_t* __restri
 // in the multi-stage sparse finish, EMS_LANES, or 1 for plans whose kept
 // segments are all at most 32 dims (one chunk: the other lanes of a group
 // would idle).  A separate instantiation, so plans with wider segments keep
-// their code and registers unchanged.
-template <bool MS, int QB, int FL = EMS_LANES>
+// their code and registers unchanged.  PK: packed k-steps for plain scans of
+// plans whose kept widths are all multiples of 16 and whose segments would
+// leave many steps half empty (see fetch_packed).
+template <bool MS, int QB, int FL = EMS_LANES, bool PK = false>
 __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
@@ -1135,10 +1137,10 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // bits of a segment the scan reads: all of them, or the first `prefix`
     // (progressive approximation, Section 3.2)
     auto used_bits = [&](int B) { return (prefix > 0 && prefix < B) ? prefix : B; };
-    auto fetch = [&](Raw& g, int si, int j0) {
-        const SegEntry e = segs[si];
-        const int W = e.width, B = used_bits(e.bits), pb = (W + 7) >> 3;
-        const int d0 = j0 + 16 * uh;
+    // plane words of this lane's 16 dims d0 .. d0 + 15 of segment e (zero
+    // past its width)
+    auto fetch_planes = [&](Raw& g, const SegEntry& e, int B, int d0) {
+        const int W = e.width, pb = (W + 7) >> 3;
         const bool any = d0 < W, two = d0 + 8 < W;
         const uint8_t* pl = rec + e.code_off + (d0 >> 3);
         // both bytes of a lane's 16 dims in one 16-bit load when they are
@@ -1158,12 +1160,21 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
             g.w[p] = w;
         }
-        if ((e.col & 7) == 0) {
-            // the scan's pre-split query (8-dim groups; dims past the
-            // segment meet zero codes, groups past D_kept are zero)
-            const u32x4* src = Qs + (int64_t(qlive ? q0 + qq : 0) * qg + ((e.col + j0 + qd) >> 3)) * 3;
+    };
+    // the scan's pre-split query of kept dims kq + qd .. kq + qd + 7 (kq a
+    // multiple of 8; dims past a segment meet zero codes, groups past D_kept
+    // are zero)
+    auto fetch_query = [&](Raw& g, int kq) {
+        const u32x4* src = Qs + (int64_t(qlive ? q0 + qq : 0) * qg + ((kq + qd) >> 3)) * 3;
 #pragma unroll
-            for (int tm = 0; tm < 3; ++tm) g.q[tm] = qlive ? src[tm] : u32x4{0u, 0u, 0u, 0u};
+        for (int tm = 0; tm < 3; ++tm) g.q[tm] = qlive ? src[tm] : u32x4{0u, 0u, 0u, 0u};
+    };
+    auto fetch = [&](Raw& g, int si, int j0) {
+        const SegEntry e = segs[si];
+        const int W = e.width, B = used_bits(e.bits);
+        fetch_planes(g, e, B, j0 + 16 * uh);
+        if ((e.col & 7) == 0) {
+            fetch_query(g, e.col + j0);
         } else {
             float qv[8];
 #pragma unroll
@@ -1182,10 +1193,9 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         // the factor changes only where a segment starts
         if (j0 == 0) g.fs = ldexpf(fr[si], e.bits - B);
     };
-    auto put = [&](const Raw& g, int si, int j0, int buf) {
-        const SegEntry e = segs[si];
-        const int W = e.width, B = used_bits(e.bits);
-        const int d0 = j0 + 16 * uh;
+    // this lane's operand from its 16 dims d0 .. d0 + 15 of a segment of
+    // width W read at B bits (zero past W), and the staged query slice
+    auto put_core = [&](const Raw& g, int W, int B, int d0, int buf) {
         uint32_t c[16];
         // loops fully unrolled with a uniform predicate per plane, so g stays
         // in registers (a loop exit would index it dynamically)
@@ -1233,6 +1243,48 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         }
 #pragma unroll
         for (int tm = 0; tm < 3; ++tm) *bq(buf, tm, qq, qd) = g.q[tm];
+    };
+    auto put = [&](const Raw& g, int si, int j0, int buf) {
+        const SegEntry e = segs[si];
+        put_core(g, e.width, used_bits(e.bits), j0 + 16 * uh, buf);
+    };
+    // Packed k-steps (PK, plain scans of plans whose kept widths are all
+    // multiples of 16): step kk covers kept dims EK kk .. EK kk + EK - 1
+    // whichever segments hold them, so a 16-dim segment no longer pads a
+    // step to 32.  The segment factor is part of each lane's operand, so the
+    // two halves of a step may belong to different segments; each lane
+    // follows its half with a cursor over the segments.
+    int seg_l = 0;
+    auto lane_seg = [&](int kk) -> int {   // -1 past D_kept
+        const int kd = EK * kk + 16 * uh;
+        if (kd >= dk) return -1;
+        while (kd >= segs[seg_l].col + segs[seg_l].width) ++seg_l;
+        return seg_l;
+    };
+    auto fetch_packed = [&](Raw& g, int kk) {
+        const int sl = lane_seg(kk);
+        if (sl >= 0) {
+            const SegEntry e = segs[sl];
+            const int B = used_bits(e.bits);
+            fetch_planes(g, e, B, EK * kk + 16 * uh - e.col);
+            g.fs = ldexpf(fr[sl], e.bits - B);
+        } else {
+#pragma unroll
+            for (int p = 0; p < 16; ++p) g.w[p] = 0u;
+            g.fs = 0.f;
+        }
+        fetch_query(g, EK * kk);
+    };
+    auto put_packed = [&](const Raw& g, int kk, int buf) {
+        const int kd = EK * kk + 16 * uh;
+        int W = 0, B = 1, d0 = 0;
+        if (kd < dk) {
+            const SegEntry e = segs[seg_l];
+            W = e.width;
+            B = used_bits(e.bits);
+            d0 = kd - e.col;
+        }
+        put_core(g, W, B, d0, buf);
     };
 
     floatx16 acc[2];
@@ -1354,7 +1406,46 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
         }
     }
-    if (go) {
+    // one k-step's products: per half m the six products of the split
+    // terms, smallest first (the projection's scheme), against queries li
+    // and 32 + li
+    auto mfma_step = [&](int buf) {
+        constexpr int TA[6] = {2, 1, 0, 1, 0, 0};
+        constexpr int TB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            u32x4 B0[3], B1[3];
+#pragma unroll
+            for (int tm = 0; tm < 3; ++tm) {
+                B0[tm] = *bq(buf, tm, li, 16 * lh + 8 * m);
+                if (QB == 2) B1[tm] = *bq(buf, tm, 32 + li, 16 * lh + 8 * m);
+            }
+#pragma unroll
+            for (int u = 0; u < 6; ++u) {
+                acc[0] = mfma_bf16(Areg[TA[u]][m], B0[TB[u]], acc[0]);
+                if (QB == 2) acc[1] = mfma_bf16(Areg[TA[u]][m], B1[TB[u]], acc[1]);
+            }
+        }
+    };
+    if constexpr (PK) {
+        static_assert(!MS, "packed k-steps are for the plain scan");
+        const int nk = (dk + EK - 1) / EK;
+        if (go && nk > 0) {
+            Raw g;
+            fetch_packed(g, 0);
+            put_packed(g, 0, 0);
+            __syncthreads();
+            for (int kt = 0;; ++kt) {
+                const int buf = kt & 1;
+                const bool more = kt + 1 < nk;
+                if (more) fetch_packed(g, kt + 1);
+                mfma_step(buf);
+                if (!more) break;
+                put_packed(g, kt + 1, buf ^ 1);
+                __syncthreads();
+            }
+        }
+    } else if (go) {
         Raw g;
         fetch(g, s, j0);
         put(g, s, j0, 0);
@@ -1377,24 +1468,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
             const bool more = s1 < n_kept;
             if (more) fetch(g, s1, j1);
-            // per half m: the six products of the split terms, smallest first
-            // (the projection's scheme), against queries li and 32 + li
-            constexpr int TA[6] = {2, 1, 0, 1, 0, 0};
-            constexpr int TB[6] = {0, 1, 2, 0, 1, 0};
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                u32x4 B0[3], B1[3];
-#pragma unroll
-                for (int tm = 0; tm < 3; ++tm) {
-                    B0[tm] = *bq(buf, tm, li, 16 * lh + 8 * m);
-                    if (QB == 2) B1[tm] = *bq(buf, tm, 32 + li, 16 * lh + 8 * m);
-                }
-#pragma unroll
-                for (int u = 0; u < 6; ++u) {
-                    acc[0] = mfma_bf16(Areg[TA[u]][m], B0[TB[u]], acc[0]);
-                    if (QB == 2) acc[1] = mfma_bf16(Areg[TA[u]][m], B1[TB[u]], acc[1]);
-                }
-            }
+            mfma_step(buf);
             if (!more) break;
             put(g, s1, j1, buf ^ 1);
             __syncthreads();
@@ -2116,14 +2190,29 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
     hipLaunchKernelGGL(split_query_kernel, dim3(unsigned((int64_t(nq) * qg + 255) / 256)), dim3(256), 0,
                        st, Qp, nq, dk, qg, Qs);
     const dim3 grid(unsigned((n + ER - 1) / ER), unsigned((nq + EQ - 1) / EQ));
-    if (nq <= 32)
-        hipLaunchKernelGGL((estimate_kernel<false, 1>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
-                           nullptr, nullptr, nullptr, nullptr, out, Qs, qg);
-    else
-        hipLaunchKernelGGL((estimate_kernel<false, 2>), grid, dim3(256), 0, st, Qp, nq, dk, qn2,
-                           dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n, int(prefix_bits),
-                           nullptr, nullptr, nullptr, nullptr, out, Qs, qg);
+    // packed k-steps when every kept segment is a whole number of 16-dim
+    // halves (each lane half then lies inside one segment) and packing saves
+    // at least a quarter of the steps: a lane's segment then varies across
+    // the wave, so its plane count and factor come from per-lane rather than
+    // uniform loads, which only pays where many steps were half padding
+    // (16-dim segments)
+    bool packed = !p->kept.empty();
+    int64_t seg_steps = 0;
+    for (const SegEntry& e : p->kept) {
+        packed = packed && (e.width % 16) == 0;
+        seg_steps += (e.width + EK - 1) / EK;
+    }
+    packed = packed && 4 * ((int64_t(dk) + EK - 1) / EK) <= 3 * seg_steps;
+#define SAQ_LAUNCH_SCAN(QB, PK)                                                                    \
+    hipLaunchKernelGGL((estimate_kernel<false, QB, EMS_LANES, PK>), grid, dim3(256), 0, st, Qp, nq, \
+                       dk, qn2, dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n,          \
+                       int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out, Qs, qg)
+    if (nq <= 32) {
+        if (packed) SAQ_LAUNCH_SCAN(1, true); else SAQ_LAUNCH_SCAN(1, false);
+    } else {
+        if (packed) SAQ_LAUNCH_SCAN(2, true); else SAQ_LAUNCH_SCAN(2, false);
+    }
+#undef SAQ_LAUNCH_SCAN
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? SAQ_OK : hip_fail(e, "estimate_kernel launch");
 }

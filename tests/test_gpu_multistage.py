@@ -103,11 +103,13 @@ def test_multistage_matches_oracle(gauss):
 
 
 def test_multistage_no_threshold_is_the_plain_scan(gauss):
-    """With tau = +inf nothing closes.  Tiles with many open pairs run the
-    plain scan's MFMA sequence and give its values bit for bit; tiles with
-    few pairs (the last query tile here: 2 queries x 128 records) take the
-    one-lane-per-pair finish from the first segment, whose sums differ
-    from the plain scan's only in order, within its FP32 tolerance."""
+    """With tau = +inf nothing closes, and every estimate equals the plain
+    scan's within the FP32 tolerance.  This plan's kept widths are multiples
+    of 16, so the plain scan packs its k-steps across segment boundaries
+    while the multi-stage scan steps segment by segment: the same products,
+    summed in another order.  Tiles with few pairs (the last query tile
+    here: 2 queries x 128 records) take the sparse finish from the first
+    segment."""
     S = gauss
     Q = S["ds"].queries(66)
     d2, st = _device_ms(S, Q, 4.0, np.full(66, np.inf))
@@ -115,12 +117,32 @@ def test_multistage_no_threshold_is_the_plain_scan(gauss):
     plain = saq.estimate_dist(S["plan"], to_dev(Q), to_dev(S["packed"]), to_dev(S["fac"]))
     torch.cuda.synchronize()
     plain = plain.cpu().numpy()
-    # full 64-query x 128-record tiles: all 8,192 pairs open, MFMA to the end
-    full = (S["packed"].shape[0] // 128) * 128
-    assert np.array_equal(d2[:64, :full], plain[:64, :full])
     scale = _scale(S, Q)
     assert np.max(np.abs(d2 - plain) / scale) < TOL
     _check(S, Q, 4.0, np.full(66, np.inf), "tau=+inf")
+
+
+def test_multistage_no_threshold_is_the_plain_scan_bit_for_bit():
+    """On a plan with kept widths that are not multiples of 16 the plain scan
+    steps segment by segment like the multi-stage scan, so with tau = +inf
+    its full 64-query x 128-record tiles (all 8,192 pairs open, matrix cores
+    to the end) give the plain scan's values bit for bit."""
+    rng = np.random.default_rng(41)
+    widths, bits = [13, 37, 70, 9, 51], [9, 6, 4, 3, 2]
+    D = sum(widths)
+    sd = np.concatenate([np.full(w, v) for w, v in zip(widths, (3.0, 2.0, 1.2, 0.9, 0.6))])
+    plan = saq.Plan.from_parts(widths, bits, np.eye(D, dtype=np.float32), np.zeros(D, np.float32),
+                               variances=sd ** 2).upload(0)
+    X = (rng.standard_normal((700, D)) * sd).astype(np.float32)
+    packed, fac, codes = oracle_records(plan, X, 4)
+    S = dict(plan=plan, P=np.eye(D), lam=sd ** 2, packed=packed, fac=fac, codes=codes)
+    Q = (rng.standard_normal((64, D)) * sd).astype(np.float32)
+    d2, st = _device_ms(S, Q, 4.0, np.full(64, np.inf))
+    assert np.all(st == len(plan.kept_widths))
+    plain = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(fac))
+    torch.cuda.synchronize()
+    full = (packed.shape[0] // 128) * 128
+    assert np.array_equal(d2[:, :full], plain.cpu().numpy()[:, :full])
 
 
 def test_multistage_everything_closes_at_stage_zero(gauss):
