@@ -258,14 +258,17 @@ def test_multistage_argument_errors(gauss):
     assert d2.shape == (0, 10) and st.shape == (0, 10)
 
 
-def test_full_size_scans_sampled():
+@pytest.mark.parametrize("which", [2, 0])
+def test_full_size_scans_sampled(which):
     """Scans in the benchmark's launch shape: 64 queries against 1,000,000
-    records at D = 768 (the scan leg's dataset shape).  The records are
-    16,384 oracle-encoded records repeated to 1M rows, so every input is the
-    oracle's; every scanned row equals its base record's estimate.  Checked
-    on a sample of 4,000 rows spread over the whole range: the plain scan,
-    the 2-bit prefix scan and the multi-stage scan (m = 4)."""
-    ds = synth.cfg5(2, 1_000_000)
+    records at D = 768 and D = 128 (the scan leg's dataset shapes; at D = 128
+    the plain scan packs its k-steps and the sparse finish takes one lane per
+    pair).  The records are 16,384 oracle-encoded records repeated to 1M
+    rows, so every input is the oracle's; every scanned row equals its base
+    record's estimate.  Checked on a sample of 4,000 rows spread over the
+    whole range: the plain scan, the 2-bit prefix scan and the multi-stage
+    scan (m = 4)."""
+    ds = synth.cfg5(which, 1_000_000)
     base_n, n, nq = 16_384, 1_000_000, 64
     Xb = ds.rows(0, base_n)
     mean, _, lam, V = oracle.pca(Xb)
@@ -284,7 +287,7 @@ def test_full_size_scans_sampled():
     scale = f64[:, -1][None, :] + ((Q.astype(np.float64) - c) ** 2).sum(1)[:, None]
     sample = np.random.default_rng(12).choice(n, 4000, replace=False)
     sb = reps[sample]
-    say("full-size scans: 64 queries x 1M records, D=768")
+    say(f"full-size scans: 64 queries x 1M records, D={ds.d}, kept widths {plan.kept_widths}")
     for label, kw, want in (("plain", {}, plain), ("prefix 2", {"prefix_bits": 2}, pre2)):
         d2 = saq.estimate_dist(plan, to_dev(Q), dev_packed, dev_fac, **kw)
         torch.cuda.synchronize()
