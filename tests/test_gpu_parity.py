@@ -208,6 +208,19 @@ def test_estimate_dist(cfg1):
     assert abs(e_gpu - e_orc) <= 0.01 * e_orc
 
 
+def half_step_plan(rng):
+    """A plan of 16- to 32-dim kept segments (9, 4, 1 and 16 bits) whose 80
+    kept dims end half way through a 32-dim step, then a dropped segment;
+    with records drawn to its scales."""
+    D = 128
+    widths, bits = [16, 32, 16, 16, 48], [9, 4, 1, 16, 0]
+    plan = saq.Plan.from_parts(widths, bits, np.eye(D, dtype=np.float32)[:80],
+                               np.zeros(D, np.float32)).upload(0)
+    Xs = (rng.standard_normal((600, D)) * np.repeat([2.0, 1.0, 0.7, 0.4, 0.2], widths)
+          ).astype(np.float32)
+    return plan, Xs
+
+
 def test_estimate_dist_shapes():
     """The estimate scan's tiles (128 records x 64 queries x 32 dims) on ragged
     shapes: query counts around 32 (one query block below it) and 64, record
@@ -227,7 +240,10 @@ def test_estimate_dist_shapes():
                              np.zeros(D, np.float32)).upload(0)
     Xw = (rng.standard_normal((700, D)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3, 0.1],
                                                      [16, 48, 32, 16, 16, 32])).astype(np.float32)
-    for plan, Xs in ((p99, X), (pw, Xw)):
+    # 80 kept dims in 16-dim steps' multiples: the plain scan packs them in
+    # three 32-dim steps, the last one half past the kept dims
+    pt, Xt = half_step_plan(rng)
+    for plan, Xs in ((p99, X), (pw, Xw), (pt, Xt)):
         for n, nq in ((1, 1), (300, 32), (300, 33), (127, 63), (129, 65), (len(Xs), 130)):
             say(f"estimate D={plan.D} n={n} nq={nq}")
             Q = (rng.standard_normal((nq, plan.D)) * Xs.std(0)).astype(np.float32)
@@ -257,7 +273,8 @@ def test_estimate_dist_prefix():
                              np.zeros(D, np.float32)).upload(0)
     Xw = (rng.standard_normal((700, D)) * np.repeat([4.0, 2.0, 1.0, 0.5, 0.3, 0.1],
                                                      [16, 48, 32, 16, 16, 32])).astype(np.float32)
-    for plan, Xs in ((p1, X), (pw, Xw)):
+    pt, Xt = half_step_plan(rng)
+    for plan, Xs in ((p1, X), (pw, Xw), (pt, Xt)):
         Q = (rng.standard_normal((70, plan.D)) * Xs.std(0)).astype(np.float32)
         packed, fac, codes = oracle_records(plan, Xs, 4)
         M, c, _ = plan.arrays()
