@@ -750,12 +750,30 @@ def multistage_timing(plan, Q, codes, fac, plain_out, ws, stream, k, m=4.0, sub=
     return res
 
 
+def scan_products_per_dim(plan, prefix_bits=0):
+    """bf16 matrix-core products the plain scan issues per kept dim and
+    query-record pair, averaged over the kept dims.  Plans whose kept widths
+    are all multiples of 16 and whose 32-dim steps would leave at least a
+    quarter of the steps to padding take packed steps with the scaled codes
+    split in three terms: six products.  Every other plan steps segment by
+    segment with the codes' c - h as one exact term (two above 8 bits read)
+    against the query's three: three products, or five."""
+    ws, bs = plan.kept_widths, plan.kept_bits
+    if not ws:
+        return 0.0
+    steps = sum((w + 31) // 32 for w in ws)
+    if all(w % 16 == 0 for w in ws) and 4 * ((sum(ws) + 31) // 32) <= 3 * steps:
+        return float(SPLIT_PRODUCTS)
+    used = [prefix_bits if 0 < prefix_bits < b else b for b in bs]
+    return sum(w * (5 if u > 8 else 3) for w, u in zip(ws, used)) / sum(ws)
+
+
 def scan_leg(a):
     """Estimate scans (Section 3.2): 64 queries against 1M stored records
     encoded at 4 b/dim, for D = 128, 768, 1536 and 3072 (variance
-    exp(-8i/D)); the scan kernel contracts the records' scaled codes with
-    the projected queries on the bf16 matrix cores, each FP32 product formed
-    from six products of exactly split operands."""
+    exp(-8i/D)); the scan kernel contracts the records' codes with the
+    projected queries on the bf16 matrix cores at FP32 accuracy (exact
+    split operands; scan_products_per_dim gives the products issued)."""
     import torch
     import synth
     import paper_2509_12086_amd as saq
@@ -788,7 +806,8 @@ def scan_leg(a):
         row = {"D": ds.d, "D_kept": plan.D_kept, "code_bytes": plan.code_bytes,
                "ms_per_scan": ms, "tflops": flops / (ms * 1e-3) / 1e12,
                "frac_bf16_mfma": flops / (ms * 1e-3) / PEAK_BF16_MFMA,
-               "issued_frac_bf16_mfma": SPLIT_PRODUCTS * flops / (ms * 1e-3) / PEAK_BF16_MFMA,
+               "bf16_products_per_fp32_product": scan_products_per_dim(plan),
+               "issued_frac_bf16_mfma": scan_products_per_dim(plan) * flops / (ms * 1e-3) / PEAK_BF16_MFMA,
                "frac_fp32_mfma": flops / (ms * 1e-3) / PEAK_FP32_MFMA,
                "record_GBps": n * (plan.code_bytes + 4 * plan.n_factors) / (ms * 1e-3) / 1e9}
         if ds.d == 3072:

@@ -932,6 +932,16 @@ __global__ __launch_bounds__(256, 2) void fused_encode_kernel(const FusedArgs ar
 // projection forms it, from the six products a_i q_j with i + j <= 2 of
 // the exact splits, accumulated in FP32: per 16-dim half and 32-query block
 // six v_mfma_f32_32x32x16_bf16 (24 per wave and k-step with two blocks).
+// That is the form of the multi-stage scan and of packed k-steps.  Plain
+// scans stepping segment by segment (TR) transpose the product instead:
+// the query terms are the A operand and each lane's own record the B
+// operand, so all 16 accumulators of a lane belong to the record it
+// unpacks.  The lane then applies f_s to its accumulators, rescaling them
+// from the previous segment's factor where a segment starts, and its
+// operand is c - (2^B - 1)/2 itself, exact as one bf16 term up to 8 bits
+// (two above): three products per 16 dims and 32-query block (five above 8
+// bits), the exact products of the query's split with the code, and no
+// FP32 scaling or split of the record's values.
 // The queries are split once per scan (split_query_kernel) when a
 // segment's first kept column is a multiple of 8, else while staging.  A
 // segment whose width is not a multiple of 32 pads its last k-step with
@@ -1080,9 +1090,15 @@ __device__ __forceinline__ float pair_segment_any(int B, const uint8_t* __restri
 // would idle).  A separate instantiation, so plans with wider segments keep
 // their code and registers unchanged.  PK: packed k-steps for plain scans of
 // plans whose kept widths are all multiples of 16 and whose segments would
-// leave many steps half empty (see fetch_packed).
-template <bool MS, int QB, int FL = EMS_LANES, bool PK = false>
-__global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
+// leave many steps half empty (see fetch_packed).  TR: plain scans
+// stepping segment by segment take the records as the B operand, so each
+// lane's accumulators belong to the one record it unpacks; the operand is
+// then c - h itself (exact in one bf16 term up to 8 bits, two up to 16) and
+// the segment factor is applied by rescaling the lane's accumulators where
+// a segment starts (see seg_start): three or five products per 16 dims
+// instead of six, and no split of the record's values.
+template <bool MS, int QB, int FL = EMS_LANES, bool PK = false, bool TR = false>
+__global__ __launch_bounds__(256, (MS || TR) ? 3 : 4) void estimate_kernel(
     const float* __restrict__ Qp, int nq, int dk, const float* __restrict__ qn2,
     const SegEntry* __restrict__ segs, int n_kept, const uint8_t* __restrict__ codes,
     int64_t code_bytes, const float* __restrict__ factors, int64_t n, int prefix,
@@ -1098,6 +1114,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         return reinterpret_cast<u32x4*>(reinterpret_cast<__bf16*>(lds) +
                                         ((b * 3 + tm) * EQ + q) * EROW + d);
     };
+    static_assert(!(TR && MS), "the multi-stage scan keeps records as the A operand");
     const int t = threadIdx.x;
     {
         uint64_t v = 0;
@@ -1131,9 +1148,16 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     // the k-step's raw inputs: plane words, the staged query dims as three
     // bf16 terms, the segment factor
     struct Raw { uint32_t w[16]; u32x4 q[3]; float fs; };
-    // this lane's A operand of the current k-step: f_s (c - h) of its 16 dims
-    // as three exact bf16 terms, for each half (dims 16 lh + 8 m .. + 7)
+    // this lane's record operand of the current k-step: f_s (c - h) of its
+    // 16 dims as three exact bf16 terms, for each half (dims 16 lh + 8 m ..
+    // + 7); the A operand, or with TR the B operand
     u32x4 Areg[3][2];
+    // TR: the record's operand is c - h as terms 0 (and 1 above 8 bits);
+    // its accumulators hold the inner products divided by gsc, the factor
+    // of the last segment taken; `use` is false in a skipped segment, whose
+    // operand is zero; fmx is the largest factor magnitude seen
+    bool use = true;
+    float gsc = 1.f, fmx = 0.f;
     // bits of a segment the scan reads: all of them, or the first `prefix`
     // (progressive approximation, Section 3.2)
     auto used_bits = [&](int B) { return (prefix > 0 && prefix < B) ? prefix : B; };
@@ -1230,16 +1254,40 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         // f_s (c - h) with h = (2^B - 1)/2; c - h is exact in FP32
         const float h = 0.5f * float((1 << B) - 1);
         float a[16];
+        if constexpr (TR) {
+            // c - h alone: 2c - (2^B - 1) is an odd integer below 2^B, so
+            // c - h has at most B significant bits, exact as one bf16 term
+            // for B <= 8 and as two (the rest below half an ulp of the
+            // first) for B <= 16
 #pragma unroll
-        for (int d = 0; d < 16; ++d) a[d] = (d0 + d < W) ? g.fs * (float(c[d]) - h) : 0.f;
+            for (int d = 0; d < 16; ++d) a[d] = (use && d0 + d < W) ? float(c[d]) - h : 0.f;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            uint32_t t0[4], t1[4], t2[4];
+            for (int m = 0; m < 2; ++m) {
+                uint32_t t0[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) split3(a[8 * m + 2 * k], a[8 * m + 2 * k + 1], t0[k], t1[k], t2[k]);
-            Areg[0][m] = u32x4{t0[0], t0[1], t0[2], t0[3]};
-            Areg[1][m] = u32x4{t1[0], t1[1], t1[2], t1[3]};
-            Areg[2][m] = u32x4{t2[0], t2[1], t2[2], t2[3]};
+                for (int k = 0; k < 4; ++k) t0[k] = pack_bf16x2(a[8 * m + 2 * k], a[8 * m + 2 * k + 1]);
+                Areg[0][m] = u32x4{t0[0], t0[1], t0[2], t0[3]};
+                uint32_t t1[4] = {0u, 0u, 0u, 0u};
+                if (B > 8) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        t1[k] = pack_bf16x2(a[8 * m + 2 * k] - __uint_as_float(t0[k] << 16),
+                                            a[8 * m + 2 * k + 1] - __uint_as_float(t0[k] & 0xffff0000u));
+                }
+                Areg[1][m] = u32x4{t1[0], t1[1], t1[2], t1[3]};
+            }
+        } else {
+#pragma unroll
+            for (int d = 0; d < 16; ++d) a[d] = (d0 + d < W) ? g.fs * (float(c[d]) - h) : 0.f;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                uint32_t t0[4], t1[4], t2[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) split3(a[8 * m + 2 * k], a[8 * m + 2 * k + 1], t0[k], t1[k], t2[k]);
+                Areg[0][m] = u32x4{t0[0], t0[1], t0[2], t0[3]};
+                Areg[1][m] = u32x4{t1[0], t1[1], t1[2], t1[3]};
+                Areg[2][m] = u32x4{t2[0], t2[1], t2[2], t2[3]};
+            }
         }
 #pragma unroll
         for (int tm = 0; tm < 3; ++tm) *bq(buf, tm, qq, qd) = g.q[tm];
@@ -1427,8 +1475,52 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             }
         }
     };
+    // TR, where segment s starts (its factor f: the lane's record's, times
+    // 2^(B - b) for a prefix): the accumulators, done with the segments
+    // before, are rescaled from gsc to f, so the products that follow need
+    // no factor.  A zero factor, or one below 2^-60 of the largest seen,
+    // skips the segment (zero operand, no rescale): its part of the inner
+    // product is then below 2^-30 of ||o|| ||q - c|| (the code's norm is at
+    // most 2^20 times another segment's, their cosines at least 2^-5), and
+    // every accumulator holds its products times at most 2^60.  A NaN
+    // factor propagates.
+    auto seg_start = [&](float f) {
+        const float af = fabsf(f);
+        fmx = fmaxf(fmx, af);
+        use = f != 0.f && !(af < 0x1p-60f * fmx);
+        // no branch around the accumulators: a skipped segment scales by 1
+        const float ratio = use ? gsc / f : 1.f;
+        gsc = use ? f : gsc;
+#pragma unroll
+        for (int b = 0; b < QB; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[b][r] *= ratio;
+    };
+    // TR: one k-step's products, the query slices (queries li and 32 + li
+    // of the tile) as the A operand and the lane's record as the B operand,
+    // smallest first; `two`: the segment's codes take two terms
+    auto mfma_step_tr = [&](int buf, bool two) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            // query term tm (2, 1, 0: smallest first) times the record's
+            // terms; q2 c1, below 2^-24 of the product, is dropped
+#pragma unroll
+            for (int tm = 2; tm >= 0; --tm) {
+                const u32x4 a0 = *bq(buf, tm, li, 16 * lh + 8 * m);
+                u32x4 a1;
+                if (QB == 2) a1 = *bq(buf, tm, 32 + li, 16 * lh + 8 * m);
+                if (two && tm < 2) {
+                    acc[0] = mfma_bf16(a0, Areg[1][m], acc[0]);
+                    if (QB == 2) acc[1] = mfma_bf16(a1, Areg[1][m], acc[1]);
+                }
+                acc[0] = mfma_bf16(a0, Areg[0][m], acc[0]);
+                if (QB == 2) acc[1] = mfma_bf16(a1, Areg[0][m], acc[1]);
+            }
+        }
+    };
     if constexpr (PK) {
         static_assert(!MS, "packed k-steps are for the plain scan");
+        static_assert(!TR, "packed k-steps take the six-product operand");
         const int nk = (dk + EK - 1) / EK;
         if (go && nk > 0) {
             Raw g;
@@ -1448,6 +1540,7 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
     } else if (go) {
         Raw g;
         fetch(g, s, j0);
+        if constexpr (TR) seg_start(g.fs);
         put(g, s, j0, 0);
         __syncthreads();
         for (int kt = 0;; ++kt) {
@@ -1468,8 +1561,14 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
             if (j1 >= segs[s1].width) { ++s1; j1 = 0; }
             const bool more = s1 < n_kept;
             if (more) fetch(g, s1, j1);
-            mfma_step(buf);
+            if constexpr (TR)
+                mfma_step_tr(buf, used_bits(segs[s].bits) > 8);
+            else
+                mfma_step(buf);
             if (!more) break;
+            if constexpr (TR) {
+                if (j1 == 0) seg_start(g.fs);
+            }
             put(g, s1, j1, buf ^ 1);
             __syncthreads();
             s = s1;
@@ -1477,11 +1576,27 @@ __global__ __launch_bounds__(256, MS ? 3 : 4) void estimate_kernel(
         }
     }
 
+    if constexpr (TR) {
+        // lane: record r0 + 32 wave + li; for register r of block bj the
+        // query q0 + 32 bj + 8 (r/4) + 4 lh + r%4, so each store writes 32
+        // consecutive records per half-wave
+        const int64_t i = r0 + 32 * wave + li;
+        if (i < n) {
+            const float o2 = factors[i * (n_kept + 1) + n_kept];
+#pragma unroll
+            for (int bj = 0; bj < QB; ++bj)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int q = q0 + 32 * bj + 8 * (r >> 2) + 4 * lh + (r & 3);
+                    if (q < nq) out[int64_t(q) * n + i] = o2 + qn2[q] - 2.f * (gsc * acc[bj][r]);
+                }
+        }
+    }
     // lane: query q0 + 32 bj + li; for register r the record
     // r0 + 32 wave + 8 (r/4) + 4 lh + r%4
     const bool vec_out = (n & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
 #pragma unroll
-    for (int bj = 0; bj < QB; ++bj) {
+    for (int bj = 0; bj < (TR ? 0 : QB); ++bj) {
         const int q = q0 + 32 * bj + li;
         if (q >= nq) continue;
         const float qn = qn2[q];
@@ -2203,14 +2318,15 @@ static saq_status scan_impl(const saq_plan* p, const float* Q, int32_t nq, const
         seg_steps += (e.width + EK - 1) / EK;
     }
     packed = packed && 4 * ((int64_t(dk) + EK - 1) / EK) <= 3 * seg_steps;
-#define SAQ_LAUNCH_SCAN(QB, PK)                                                                    \
-    hipLaunchKernelGGL((estimate_kernel<false, QB, EMS_LANES, PK>), grid, dim3(256), 0, st, Qp, nq, \
-                       dk, qn2, dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n,          \
+    // otherwise segment by segment with the records as the B operand (TR)
+#define SAQ_LAUNCH_SCAN(QB, PK, TR)                                                                 \
+    hipLaunchKernelGGL((estimate_kernel<false, QB, EMS_LANES, PK, TR>), grid, dim3(256), 0, st, Qp, \
+                       nq, dk, qn2, dev_seg(p), p->n_kept, codes, p->code_bytes, factors, n,       \
                        int(prefix_bits), nullptr, nullptr, nullptr, nullptr, out, Qs, qg)
     if (nq <= 32) {
-        if (packed) SAQ_LAUNCH_SCAN(1, true); else SAQ_LAUNCH_SCAN(1, false);
+        if (packed) SAQ_LAUNCH_SCAN(1, true, false); else SAQ_LAUNCH_SCAN(1, false, true);
     } else {
-        if (packed) SAQ_LAUNCH_SCAN(2, true); else SAQ_LAUNCH_SCAN(2, false);
+        if (packed) SAQ_LAUNCH_SCAN(2, true, false); else SAQ_LAUNCH_SCAN(2, false, true);
     }
 #undef SAQ_LAUNCH_SCAN
     const hipError_t e = hipGetLastError();

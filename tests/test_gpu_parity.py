@@ -258,6 +258,61 @@ def test_estimate_dist_shapes():
             assert np.max(np.abs(d2 - ref) / scale) < 2e-5
 
 
+def test_estimate_dist_factor_extremes():
+    """Segment factors the plain scan's rescaling must handle (it applies
+    f_s by scaling its partial sums from one segment's factor to the next):
+    zero factors, factors 2^-70 of another segment's (skipped, their part
+    below 2^-30 of the scale), 2^+-50 jumps, a first segment far below the
+    rest, all-zero records, a negative factor, and a NaN factor, which must
+    give NaN.  Checked against the oracle's estimator on the same records and
+    factors, for 5 and 40 queries and for a 3-bit prefix; the plan (widths
+    20, 37, 40, 9; 16, 9, 4 and 2 bits) steps segment by segment, with one-
+    and two-term codes.  FP32 tolerance relative to ||o||^2 + ||q - c||^2 +
+    2 sum_s |f_s| ||u_s|| ||q_s||, the size of the terms summed (with real
+    factors f_s ||u_s|| is about ||o_s||; a scaled factor scales the terms,
+    and the inner product may cancel far below them)."""
+    rng = np.random.default_rng(77)
+    widths, bits = [20, 37, 40, 9], [16, 9, 4, 2]
+    D = sum(widths)
+    plan = saq.Plan.from_parts(widths, bits, np.eye(D, dtype=np.float32),
+                               np.zeros(D, np.float32)).upload(0)
+    sd = np.repeat([3.0, 1.5, 1.0, 0.5], widths)
+    X = (rng.standard_normal((300, D)) * sd).astype(np.float32)
+    packed, fac, codes = oracle_records(plan, X, 4)
+    f = fac.copy()
+    f[0:10, 1] *= 2.0 ** -70
+    f[10:20, 0] *= 2.0 ** -70
+    f[20:30, 2] *= 2.0 ** 50
+    f[30:40, 1] = 0.0
+    f[40:50, :-1] = 0.0
+    f[50:60, 1] *= 2.0 ** -50
+    f[60:70, 0] *= 2.0 ** 50
+    f[60:70, 1] *= 2.0 ** -50
+    f[70, 1] = -f[70, 1]
+    f[71, 2] = np.nan
+    f[72:80, 0] = 0.0
+    f[72:80, 3] *= 2.0 ** 40
+    h = np.concatenate([np.full(w, 0.5 * (2 ** b - 1)) for w, b in zip(widths, bits)])
+    edges = np.cumsum([0] + widths)
+    unorm = np.stack([np.linalg.norm((codes - h)[:, a:b], axis=1) for a, b in zip(edges, edges[1:])], 1)
+    for nq, prefix in ((5, 0), (40, 0), (40, 3)):
+        say(f"estimate factor extremes nq={nq} prefix={prefix}")
+        Q = (rng.standard_normal((nq, D)) * sd).astype(np.float32)
+        d2 = saq.estimate_dist(plan, to_dev(Q), to_dev(packed), to_dev(f), prefix_bits=prefix)
+        torch.cuda.synchronize()
+        d2 = d2.cpu().numpy()
+        ref = oracle_scan(plan, Q, codes, f, prefix_bits=prefix)
+        nan = np.isnan(ref)
+        assert np.array_equal(np.isnan(d2), nan) and nan[:, 71].all() and nan.sum() == nq
+        qnorm = np.stack([np.linalg.norm(Q[:, a:b].astype(np.float64), axis=1)
+                          for a, b in zip(edges, edges[1:])], 1)
+        mag = qnorm @ (np.abs(f[:, :-1].astype(np.float64)) * unorm).T
+        sc = f[:, -1][None, :] + (Q.astype(np.float64) ** 2).sum(1)[:, None] + 2 * mag
+        err = np.abs(d2 - ref)[~nan] / sc[~nan]
+        say(f"  max err {err.max():.2e}")
+        assert err.max() < 2e-5
+
+
 def test_estimate_dist_prefix():
     """Progressive estimation from code prefixes (Section 3.2): for several
     prefix lengths the scan equals the oracle's prefix estimator on the same
