@@ -105,3 +105,29 @@ def test_clock_figures_follow_the_recorded_cycles():
     leg = {"plan": plan, "n": 1000, "bpd": 4.0, "proj_ms": 1.0, "quant_ms": 1.0, "ms_step": 2.0}
     r = bench.kernel_records(SimpleNamespace(rounds=0), leg)
     assert "valu" not in r["end_to_end"]["roofline_vectors_per_s"]
+
+
+def test_scan_products_per_dim_follows_the_scan_path():
+    """The bf16 products the bench counts per FP32 product: six for plans the
+    scan runs with packed k-steps (kept widths all multiples of 16, packing
+    saving at least a quarter of the 32-dim steps), otherwise three per dim,
+    five in segments with more than 8 bits read, averaged over the kept dims."""
+    import numpy as np
+    import paper_2509_12086_amd as saq
+
+    def plan(widths, bits):
+        D = sum(widths)
+        k = sum(w for w, b in zip(widths, bits) if b > 0)
+        return saq.Plan.from_parts(widths, bits, np.eye(D, dtype=np.float32)[:k], np.zeros(D, np.float32))
+
+    # six 16-dim segments: 3 packed steps instead of 6
+    assert bench.scan_products_per_dim(plan([16] * 6, [9, 7, 6, 5, 3, 2])) == 6.0
+    # multiples of 16 where packing saves under a quarter: segment by segment
+    p = plan([64, 48, 32], [9, 4, 2])
+    assert bench.scan_products_per_dim(p) == (64 * 5 + 48 * 3 + 32 * 3) / 144
+    # ragged widths; a prefix of 3 bits reads no segment above 8 bits
+    p = plan([13, 37, 70, 9], [16, 9, 4, 2])
+    assert bench.scan_products_per_dim(p) == (13 * 5 + 37 * 5 + 70 * 3 + 9 * 3) / 129
+    assert bench.scan_products_per_dim(p, prefix_bits=3) == 3.0
+    # a dropped trailing segment does not count
+    assert bench.scan_products_per_dim(plan([20, 12], [3, 0])) == 3.0
